@@ -1,0 +1,151 @@
+"""ctypes front end of the FP64 E-A-HALS oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark use this package. The GPU library neither imports nor links it.
+Inputs are promoted to float64 here; outputs are float64 numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+OK, EINVAL, ENUMERIC, ENOMEM = 0, 1, 2, 3
+BETABAR_LAST_ACCEPTED = 1
+CMP_LAST_ACCEPTED = 2
+ERR_REMARK1 = 4
+
+_lib = None
+
+
+class _Matrix(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64),
+                ("dense", C.c_void_p), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("hp", C.c_int), ("beta0", C.c_double), ("gamma", C.c_double),
+                ("gamma_bar", C.c_double), ("eta", C.c_double),
+                ("inner_k", C.c_int), ("max_iter", C.c_int),
+                ("tol", C.c_double), ("flags", C.c_int),
+                ("replay", C.c_void_p)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        _lib = C.CDLL(LIB)
+        d, i, p = C.c_double, C.c_int, C.c_void_p
+        _lib.oracle_eahals.argtypes = [p, i, p, p, p, p, p, p, p, p, p, p]
+        _lib.oracle_eahals.restype = i
+        _lib.oracle_nnls_h.argtypes = [p, i, p, p, i]
+        _lib.oracle_nnls_w.argtypes = [p, i, p, p, i]
+        _lib.oracle_beta_script.argtypes = [i, p, d, d, d, d, i, p, p]
+        _lib.oracle_beta_script.restype = None
+        _lib.oracle_rel_error.argtypes = [p, i, p, p]
+        _lib.oracle_rel_error.restype = d
+        _lib.oracle_rel_error_remark1.argtypes = [p, i, p, p]
+        _lib.oracle_rel_error_remark1.restype = d
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class _Held:
+    """Keeps the float64 copies alive while C holds pointers to them."""
+
+    def __init__(self, X):
+        if hasattr(X, "row_ptr"):
+            self.row_ptr = np.ascontiguousarray(X.row_ptr, dtype=np.int64)
+            self.col_idx = np.ascontiguousarray(X.col_idx, dtype=np.int32)
+            self.val = np.ascontiguousarray(X.val, dtype=np.float64)
+            self.s = _Matrix(X.m, X.n, None, _ptr(self.row_ptr).value,
+                             _ptr(self.col_idx).value, _ptr(self.val).value)
+        else:
+            self.dense = np.ascontiguousarray(X, dtype=np.float64)
+            m, n = self.dense.shape
+            self.s = _Matrix(m, n, _ptr(self.dense).value, None, None, None)
+        self.m, self.n = self.s.m, self.s.n
+
+
+def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
+          eta=1.5, inner_k=10, max_iter=100, tol=0.0, flags=0, replay=None):
+    """Run Alg. 2 with Alg. 3 and return a dict with W, H (last accepted),
+    trace (rho(0..n_iter)), accepted, beta, margin and n_iter."""
+    h = _Held(X)
+    W0 = np.ascontiguousarray(W0, dtype=np.float64).reshape(h.m, r)
+    H0 = np.ascontiguousarray(H0, dtype=np.float64).reshape(r, h.n)
+    W = np.empty_like(W0)
+    H = np.empty_like(H0)
+    trace = np.zeros(max_iter + 1)
+    acc = np.zeros(max(max_iter, 1), dtype=np.uint8)
+    beta = np.zeros(max(max_iter, 1))
+    margin = np.zeros(max(max_iter, 1))
+    rp = None
+    if replay is not None:
+        rp = np.ascontiguousarray(replay, dtype=np.uint8)
+        if rp.size < max_iter:
+            raise ValueError("replay needs max_iter decisions")
+    prm = _Params(hp, beta0, gamma, gamma_bar, eta, inner_k, max_iter, tol,
+                  flags, None if rp is None else _ptr(rp).value)
+    nit = C.c_int(0)
+    st = lib().oracle_eahals(C.byref(h.s), r, _ptr(W0), _ptr(H0), C.byref(prm),
+                             _ptr(W), _ptr(H), _ptr(trace), _ptr(acc),
+                             _ptr(beta), _ptr(margin), C.byref(nit))
+    if st != OK:
+        raise RuntimeError(f"oracle_eahals failed with status {st}")
+    k = nit.value
+    return dict(W=W, H=H, trace=trace[:k + 1], accepted=acc[:k].astype(bool),
+                beta=beta[:k], margin=margin[:k], n_iter=k)
+
+
+def nnls_h(X, W, H0, sweeps):
+    h = _Held(X)
+    r = W.shape[1]
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    H = np.array(H0, dtype=np.float64, order="C", copy=True)
+    if lib().oracle_nnls_h(C.byref(h.s), r, _ptr(W), _ptr(H), sweeps) != OK:
+        raise RuntimeError("oracle_nnls_h failed")
+    return H
+
+
+def nnls_w(X, H, W0, sweeps):
+    h = _Held(X)
+    r = H.shape[0]
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    W = np.array(W0, dtype=np.float64, order="C", copy=True)
+    if lib().oracle_nnls_w(C.byref(h.s), r, _ptr(H), _ptr(W), sweeps) != OK:
+        raise RuntimeError("oracle_nnls_w failed")
+    return W
+
+
+def beta_script(decreased, beta0, gamma, gamma_bar, eta, flags=0):
+    d = np.ascontiguousarray(decreased, dtype=np.uint8)
+    bu = np.zeros(d.size)
+    bb = np.zeros(d.size)
+    lib().oracle_beta_script(d.size, _ptr(d), beta0, gamma, gamma_bar, eta,
+                             flags, _ptr(bu), _ptr(bb))
+    return bu, bb
+
+
+def rel_error(X, W, H):
+    h = _Held(X)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    return lib().oracle_rel_error(C.byref(h.s), W.shape[1], _ptr(W), _ptr(H))
+
+
+def rel_error_remark1(X, W, H):
+    h = _Held(X)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    return lib().oracle_rel_error_remark1(C.byref(h.s), W.shape[1], _ptr(W),
+                                          _ptr(H))

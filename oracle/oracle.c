@@ -1,0 +1,415 @@
+/*
+ * FP64 oracle for extrapolated accelerated HALS (E-A-HALS), arXiv 1805.06604.
+ * TEST INFRASTRUCTURE ONLY: see oracle.h for the contract and the readings.
+ *
+ * Every routine is a plain loop nest in double precision, single threaded,
+ * with a fixed summation order. Nothing here is blocked, fused or reordered
+ * beyond what the paper's formulas state.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- products */
+
+static int is_csr(const oracle_matrix *X) { return X->dense == NULL; }
+
+/* ||X||_F^2 (Remark 1: computed once). */
+static double frob2(const oracle_matrix *X)
+{
+    double s = 0.0;
+    if (!is_csr(X)) {
+        for (int64_t i = 0; i < X->m * X->n; ++i) s += X->dense[i] * X->dense[i];
+    } else {
+        for (int64_t p = 0; p < X->row_ptr[X->m]; ++p) s += X->val[p] * X->val[p];
+    }
+    return s;
+}
+
+/* C = W^T X (r x n): the linear term of the H update (section 1). */
+static void wt_x(const oracle_matrix *X, int r, const double *W, double *C)
+{
+    const int64_t m = X->m, n = X->n;
+    memset(C, 0, sizeof(double) * (size_t)r * (size_t)n);
+    for (int64_t i = 0; i < m; ++i) {
+        if (!is_csr(X)) {
+            const double *xi = X->dense + i * n;
+            for (int k = 0; k < r; ++k) {
+                const double w = W[i * r + k];
+                double *ck = C + (int64_t)k * n;
+                for (int64_t j = 0; j < n; ++j) ck[j] += w * xi[j];
+            }
+        } else {
+            for (int64_t p = X->row_ptr[i]; p < X->row_ptr[i + 1]; ++p) {
+                const int64_t j = X->col_idx[p];
+                for (int k = 0; k < r; ++k)
+                    C[(int64_t)k * n + j] += W[i * r + k] * X->val[p];
+            }
+        }
+    }
+}
+
+/* A = X H^T (m x r): the linear term of the W update (Remark 1). */
+static void x_ht(const oracle_matrix *X, int r, const double *H, double *A)
+{
+    const int64_t m = X->m, n = X->n;
+    for (int64_t i = 0; i < m; ++i) {
+        for (int k = 0; k < r; ++k) {
+            const double *hk = H + (int64_t)k * n;
+            double s = 0.0;
+            if (!is_csr(X)) {
+                const double *xi = X->dense + i * n;
+                for (int64_t j = 0; j < n; ++j) s += xi[j] * hk[j];
+            } else {
+                for (int64_t p = X->row_ptr[i]; p < X->row_ptr[i + 1]; ++p)
+                    s += X->val[p] * hk[X->col_idx[p]];
+            }
+            A[i * r + k] = s;
+        }
+    }
+}
+
+/* G = W^T W (r x r), W m x r. */
+static void gram_cols(int64_t m, int r, const double *W, double *G)
+{
+    for (int k = 0; k < r; ++k)
+        for (int l = 0; l < r; ++l) {
+            double s = 0.0;
+            for (int64_t i = 0; i < m; ++i) s += W[i * r + k] * W[i * r + l];
+            G[k * r + l] = s;
+        }
+}
+
+/* B = H H^T (r x r), H r x n. */
+static void gram_rows(int64_t n, int r, const double *H, double *B)
+{
+    for (int k = 0; k < r; ++k)
+        for (int l = 0; l < r; ++l) {
+            double s = 0.0;
+            for (int64_t j = 0; j < n; ++j) s += H[k * n + j] * H[l * n + j];
+            B[k * r + l] = s;
+        }
+}
+
+/* ------------------------------------------------------------- HALS sweeps */
+
+/* One pass over the rows of H, each replaced by its exact minimizer with the
+ * other rows fixed (the closed form of section 1):
+ *   H(k,:) = max(0, (C(k,:) - sum_{j != k} G(k,j) H(j,:)) / G(k,k)),
+ * with C = W^T X and G = W^T W. Rows are visited in ascending k and the
+ * updated rows are used at once (Gauss-Seidel). A zero G(k,k) keeps the row
+ * (R10). */
+static void hals_rows_h(int64_t n, int r, const double *C, const double *G,
+                        double *H)
+{
+    for (int k = 0; k < r; ++k) {
+        const double d = G[k * r + k];
+        if (!(d > 0.0)) continue;
+        for (int64_t c = 0; c < n; ++c) {
+            double num = C[(int64_t)k * n + c];
+            for (int j = 0; j < r; ++j)
+                if (j != k) num -= G[k * r + j] * H[(int64_t)j * n + c];
+            const double v = num / d;
+            H[(int64_t)k * n + c] = v > 0.0 ? v : 0.0;
+        }
+    }
+}
+
+/* The same for the columns of W, by the symmetry ||X - WH|| = ||X^T - H^T W^T||:
+ *   W(:,k) = max(0, (A(:,k) - sum_{j != k} W(:,j) B(j,k)) / B(k,k)),
+ * with A = X H^T and B = H H^T. */
+static void hals_cols_w(int64_t m, int r, const double *A, const double *B,
+                        double *W)
+{
+    for (int k = 0; k < r; ++k) {
+        const double d = B[k * r + k];
+        if (!(d > 0.0)) continue;
+        for (int64_t i = 0; i < m; ++i) {
+            double num = A[i * r + k];
+            for (int j = 0; j < r; ++j)
+                if (j != k) num -= W[i * r + j] * B[j * r + k];
+            const double v = num / d;
+            W[i * r + k] = v > 0.0 ? v : 0.0;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ errors */
+
+static double explicit_err2(const oracle_matrix *X, int r, const double *W,
+                            const double *H)
+{
+    const int64_t m = X->m, n = X->n;
+    double s = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t p = is_csr(X) ? X->row_ptr[i] : 0;
+        const int64_t pend = is_csr(X) ? X->row_ptr[i + 1] : 0;
+        for (int64_t j = 0; j < n; ++j) {
+            double x = 0.0;
+            if (!is_csr(X)) {
+                x = X->dense[i * n + j];
+            } else if (p < pend && X->col_idx[p] == j) {
+                x = X->val[p];
+                ++p;
+            }
+            double wh = 0.0;
+            for (int k = 0; k < r; ++k) wh += W[i * r + k] * H[(int64_t)k * n + j];
+            const double d = x - wh;
+            s += d * d;
+        }
+    }
+    return s;
+}
+
+/* Remark 1: ||X - WH||^2 = ||X||^2 - 2 <W, X H^T> + <W^T W, H H^T>, given
+ * A = X H^T and B = H H^T. Clamped at 0 before the square root. */
+static double remark1_err2(int64_t m, int r, double nx2, const double *W,
+                           const double *A, const double *B)
+{
+    double s1 = 0.0;
+    for (int64_t i = 0; i < m * r; ++i) s1 += W[i] * A[i];
+    double *G = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+    gram_cols(m, r, W, G);
+    double s2 = 0.0;
+    for (int i = 0; i < r * r; ++i) s2 += G[i] * B[i];
+    free(G);
+    return nx2 - 2.0 * s1 + s2;
+}
+
+/* ---------------------------------------------------------- beta (Alg. 3) */
+
+typedef struct {
+    double beta;       /* beta_k: used in the current iteration            */
+    double betabar;    /* upper bound                                      */
+    double beta_prev;  /* beta_{k-1}                                       */
+    double beta_acc;   /* beta of the most recent accepted iteration       */
+} beta_state;
+
+static void beta_init(beta_state *s, double beta0)
+{
+    s->beta = beta0;
+    s->betabar = 1.0;          /* R4: once per solve */
+    s->beta_prev = beta0;      /* R5: for k = 1, beta_{k-1} is beta0 */
+    s->beta_acc = beta0;
+}
+
+static void beta_update(beta_state *s, int decreased, double gamma,
+                        double gamma_bar, double eta, int flags)
+{
+    const double bk = s->beta;
+    double next;
+    if (decreased) {
+        next = fmin(s->betabar, gamma * bk);
+        s->betabar = fmin(1.0, gamma_bar * s->betabar);   /* R3 */
+        s->beta_acc = bk;
+    } else {
+        next = bk / eta;                                   /* R2 */
+        s->betabar = (flags & ORACLE_BETABAR_LAST_ACCEPTED) ? s->beta_acc
+                                                            : s->beta_prev;  /* R5 */
+    }
+    s->beta_prev = bk;
+    s->beta = next;
+}
+
+void oracle_beta_script(int count, const uint8_t *decreased, double beta0,
+                        double gamma, double gamma_bar, double eta, int flags,
+                        double *beta_used, double *betabar_after)
+{
+    beta_state s;
+    beta_init(&s, beta0);
+    for (int k = 0; k < count; ++k) {
+        beta_used[k] = s.beta;
+        beta_update(&s, decreased[k] != 0, gamma, gamma_bar, eta, flags);
+        betabar_after[k] = s.betabar;
+    }
+}
+
+/* ------------------------------------------------------------------- solve */
+
+static int valid_matrix(const oracle_matrix *X)
+{
+    if (X == NULL || X->m < 1 || X->n < 1) return 0;
+    if (!is_csr(X)) return 1;
+    if (X->row_ptr == NULL || X->row_ptr[0] != 0) return 0;
+    for (int64_t i = 0; i < X->m; ++i) {
+        if (X->row_ptr[i + 1] < X->row_ptr[i]) return 0;
+        for (int64_t p = X->row_ptr[i]; p < X->row_ptr[i + 1]; ++p) {
+            if (X->col_idx[p] < 0 || X->col_idx[p] >= X->n) return 0;
+            if (p > X->row_ptr[i] && X->col_idx[p] <= X->col_idx[p - 1]) return 0;
+        }
+    }
+    return 1;
+}
+
+/* Extrapolation: Y = N + beta (N - P), optionally projected onto Y >= 0. */
+static void extrapolate(int64_t len, double beta, const double *N,
+                        const double *P, double *Y, int project)
+{
+    for (int64_t i = 0; i < len; ++i) {
+        double v = N[i] + beta * (N[i] - P[i]);
+        if (project && v < 0.0) v = 0.0;
+        Y[i] = v;
+    }
+}
+
+int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
+                  const double *H0, const oracle_params *p, double *W,
+                  double *H, double *trace, uint8_t *accepted,
+                  double *beta_used, double *margin, int *n_iter)
+{
+    if (!valid_matrix(X) || r < 1 || p == NULL || p->hp < 1 || p->hp > 3 ||
+        p->max_iter < 0 || p->inner_k < 1)
+        return ORACLE_EINVAL;
+    const int64_t m = X->m, n = X->n;
+    const int64_t mr = m * r, rn = (int64_t)r * n;
+    const double nx2 = frob2(X);
+    if (!(nx2 > 0.0) || !isfinite(nx2)) return ORACLE_EINVAL;
+    const double nx = sqrt(nx2);
+
+    double *Wy = malloc(sizeof(double) * mr), *Wn = malloc(sizeof(double) * mr);
+    double *Wyn = malloc(sizeof(double) * mr), *A = malloc(sizeof(double) * mr);
+    double *Hy = malloc(sizeof(double) * rn), *Hn = malloc(sizeof(double) * rn);
+    double *Hyn = malloc(sizeof(double) * rn), *C = malloc(sizeof(double) * rn);
+    double *G = malloc(sizeof(double) * r * r), *B = malloc(sizeof(double) * r * r);
+    int status = ORACLE_OK;
+    if (!Wy || !Wn || !Wyn || !A || !Hy || !Hn || !Hyn || !C || !G || !B) {
+        status = ORACLE_ENOMEM;
+        goto done;
+    }
+
+    /* Alg. 2, first step: W_y = W, H_y = H, e(0) = ||X - W H||_F. */
+    memcpy(W, W0, sizeof(double) * mr);
+    memcpy(H, H0, sizeof(double) * rn);
+    memcpy(Wy, W, sizeof(double) * mr);
+    memcpy(Hy, H, sizeof(double) * rn);
+    double e0;
+    if (p->flags & ORACLE_ERR_REMARK1) {
+        x_ht(X, r, H, A);
+        gram_rows(n, r, H, B);
+        e0 = sqrt(fmax(0.0, remark1_err2(m, r, nx2, W, A, B)));
+    } else {
+        e0 = sqrt(explicit_err2(X, r, W, H));
+    }
+    if (!isfinite(e0)) { status = ORACLE_ENUMERIC; goto done; }
+    trace[0] = e0 / nx;
+
+    beta_state bs;
+    beta_init(&bs, p->beta0);
+    double e_prev = e0, e_acc = e0;
+    int k = 0;
+    for (k = 1; k <= p->max_iter; ++k) {
+        const double beta = bs.beta;
+
+        /* H_n: NNLS in H with W_y fixed, warm-started at H_y. */
+        wt_x(X, r, Wy, C);
+        gram_cols(m, r, Wy, G);
+        memcpy(Hn, Hy, sizeof(double) * rn);
+        for (int s = 0; s < p->inner_k; ++s) hals_rows_h(n, r, C, G, Hn);
+
+        /* hp >= 2: extrapolate H now (hp = 3: and project). R6: for hp = 1
+         * the same H_y is formed after the W update and only warm-starts the
+         * next H update; its value does not depend on that placement. */
+        extrapolate(rn, beta, Hn, H, Hyn, p->hp == 3);
+        const double *Hw = (p->hp == 1) ? Hn : Hyn;
+
+        /* W_n: NNLS in W with H_w fixed, warm-started at W_y. */
+        x_ht(X, r, Hw, A);
+        gram_rows(n, r, Hw, B);
+        memcpy(Wn, Wy, sizeof(double) * mr);
+        for (int s = 0; s < p->inner_k; ++s) hals_cols_w(m, r, A, B, Wn);
+
+        /* W_y = W_n + beta (W_n - W). */
+        extrapolate(mr, beta, Wn, W, Wyn, 0);
+
+        /* e(k) = ||X - W_n H_w||_F. */
+        double e2 = (p->flags & ORACLE_ERR_REMARK1)
+                        ? fmax(0.0, remark1_err2(m, r, nx2, Wn, A, B))
+                        : explicit_err2(X, r, Wn, Hw);
+        const double e = sqrt(e2);
+        trace[k] = e / nx;
+
+        const double e_cmp = (p->flags & ORACLE_CMP_LAST_ACCEPTED) ? e_acc : e_prev;
+        int decreased = isfinite(e) && !(e > e_cmp);          /* R7, R8, R9 */
+        if (margin) margin[k - 1] = (e - e_cmp) / nx;
+        if (p->replay) decreased = p->replay[k - 1] != 0;
+        if (beta_used) beta_used[k - 1] = beta;
+        if (accepted) accepted[k - 1] = (uint8_t)decreased;
+
+        if (decreased) {
+            memcpy(W, Wn, sizeof(double) * mr);
+            memcpy(H, Hn, sizeof(double) * rn);
+            memcpy(Wy, Wyn, sizeof(double) * mr);
+            memcpy(Hy, Hyn, sizeof(double) * rn);
+            e_acc = e;
+        } else {
+            /* Restart: the extrapolated sequence goes back to (W, H). */
+            memcpy(Wy, W, sizeof(double) * mr);
+            memcpy(Hy, H, sizeof(double) * rn);
+        }
+        beta_update(&bs, decreased, p->gamma, p->gamma_bar, p->eta, p->flags);
+        if (isfinite(e)) e_prev = e;
+
+        if (p->tol > 0.0 && decreased && fabs(trace[k] - trace[k - 1]) < p->tol) {
+            ++k;
+            break;
+        }
+    }
+    *n_iter = k - 1;
+
+done:
+    free(Wy); free(Wn); free(Wyn); free(A);
+    free(Hy); free(Hn); free(Hyn); free(C);
+    free(G); free(B);
+    return status;
+}
+
+/* ------------------------------------------------------------ NNLS entries */
+
+int oracle_nnls_h(const oracle_matrix *X, int r, const double *W, double *H,
+                  int sweeps)
+{
+    if (!valid_matrix(X) || r < 1) return ORACLE_EINVAL;
+    const int64_t rn = (int64_t)r * X->n;
+    double *C = malloc(sizeof(double) * rn), *G = malloc(sizeof(double) * r * r);
+    if (!C || !G) { free(C); free(G); return ORACLE_ENOMEM; }
+    wt_x(X, r, W, C);
+    gram_cols(X->m, r, W, G);
+    for (int s = 0; s < sweeps; ++s) hals_rows_h(X->n, r, C, G, H);
+    free(C); free(G);
+    return ORACLE_OK;
+}
+
+int oracle_nnls_w(const oracle_matrix *X, int r, const double *H, double *W,
+                  int sweeps)
+{
+    if (!valid_matrix(X) || r < 1) return ORACLE_EINVAL;
+    const int64_t mr = X->m * r;
+    double *A = malloc(sizeof(double) * mr), *B = malloc(sizeof(double) * r * r);
+    if (!A || !B) { free(A); free(B); return ORACLE_ENOMEM; }
+    x_ht(X, r, H, A);
+    gram_rows(X->n, r, H, B);
+    for (int s = 0; s < sweeps; ++s) hals_cols_w(X->m, r, A, B, W);
+    free(A); free(B);
+    return ORACLE_OK;
+}
+
+double oracle_rel_error(const oracle_matrix *X, int r, const double *W,
+                        const double *H)
+{
+    return sqrt(explicit_err2(X, r, W, H) / frob2(X));
+}
+
+double oracle_rel_error_remark1(const oracle_matrix *X, int r, const double *W,
+                                const double *H)
+{
+    const int64_t m = X->m;
+    double *A = malloc(sizeof(double) * m * r), *B = malloc(sizeof(double) * r * r);
+    x_ht(X, r, H, A);
+    gram_rows(X->n, r, H, B);
+    const double nx2 = frob2(X);
+    const double e2 = remark1_err2(m, r, nx2, W, A, B);
+    free(A); free(B);
+    return sqrt(fmax(0.0, e2) / nx2);
+}

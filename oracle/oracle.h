@@ -1,0 +1,117 @@
+/*
+ * FP64 reference implementation of extrapolated accelerated HALS (E-A-HALS),
+ * Ang & Gillis, "Accelerating Nonnegative Matrix Factorization Algorithms
+ * using Extrapolation" (arXiv 1805.06604).
+ *
+ * TEST INFRASTRUCTURE ONLY. This library is the oracle that the GPU path is
+ * checked against. It is plain, single-threaded, double-precision C with
+ * fixed summation orders, no BLAS and no fast-math. Only the test suite, the
+ * smoke check and the CPU baseline of the benchmark may load it; the GPU
+ * library never links or calls it, and the two share no code.
+ *
+ * Layouts: X is m x n (dense row-major, or CSR with sorted column indices),
+ * W is m x r row-major, H is r x n row-major (the paper's notation).
+ *
+ * Readings of the paper that this code takes (numbered like the list of
+ * readings kept with the design notes):
+ *   R1  H is r x n (the REQUIRE lines of Algorithms 1 and 2 print m x r).
+ *   R2  Alg. 3 sets beta_{k+1} = beta_k / eta on an increase (its printed
+ *       line duplicates the left-hand side).
+ *   R3  The upper bound grows by gamma_bar on a decrease (Alg. 3; the
+ *       prose of section 4 prints gamma there).
+ *   R4  beta0 is the beta used in outer iteration 1; the upper bound starts
+ *       at 1 once per solve (section 4, first paragraph after Alg. 3).
+ *   R5  On an increase the upper bound becomes the beta used in iteration
+ *       k-1 (for k = 1: beta0). ORACLE_BETABAR_LAST_ACCEPTED instead uses
+ *       the beta of the most recent accepted iteration.
+ *   R6  For hp = 1 the W update and e(k) use H_n; H_y = H_n + beta (H_n - H)
+ *       is only the warm start of the next H update (section 3, "When
+ *       should we perform the extrapolation?").
+ *   R7  e(k) is compared with the previous computed finite e, accepted or
+ *       not; ORACLE_CMP_LAST_ACCEPTED compares with the last accepted e.
+ *   R8  Equality accepts (the test of Alg. 2 is a strict ">").
+ *   R9  A non-finite e(k) is a restart and does not replace the previous e;
+ *       a non-finite e(0) is an error (ORACLE_ENUMERIC).
+ *   R10 A HALS coordinate whose denominator ||W(:,k)||^2 (or ||H(k,:)||^2)
+ *       is zero keeps its value; rows/columns are visited in ascending k.
+ *   R11 The output is the last accepted (W, H).
+ *   R12 tol > 0 stops after an accepted iteration k with
+ *       |rho(k) - rho(k-1)| < tol; rho = e / ||X||_F.
+ *   R13 The inner NNLS runs a fixed number K of HALS sweeps per block.
+ */
+#ifndef NMF_ORACLE_H
+#define NMF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORACLE_OK       0
+#define ORACLE_EINVAL   1
+#define ORACLE_ENUMERIC 2
+#define ORACLE_ENOMEM   3
+
+#define ORACLE_BETABAR_LAST_ACCEPTED 1  /* R5 alternative */
+#define ORACLE_CMP_LAST_ACCEPTED     2  /* R7 alternative */
+#define ORACLE_ERR_REMARK1           4  /* e(k) by Remark 1 instead of the explicit residual */
+
+typedef struct {
+    int64_t m, n;
+    const double  *dense;    /* m*n row-major, or NULL for CSR          */
+    const int64_t *row_ptr;  /* CSR: m+1 offsets                        */
+    const int32_t *col_idx;  /* CSR: sorted, unique per row             */
+    const double  *val;      /* CSR: nonzero values                     */
+} oracle_matrix;
+
+typedef struct {
+    int    hp;                /* 1, 2 or 3 (Alg. 2)                       */
+    double beta0, gamma, gamma_bar, eta;  /* Alg. 3                         */
+    int    inner_k;           /* HALS sweeps per block update (R13)       */
+    int    max_iter;
+    double tol;               /* R12; 0 disables                          */
+    int    flags;             /* ORACLE_* flags above                     */
+    const uint8_t *replay;    /* NULL, or max_iter forced decisions
+                                 (1 accept, 0 restart): decision replay   */
+} oracle_params;
+
+/* Full solve (Alg. 2 with Alg. 3). Outputs, all caller-allocated:
+ *   W (m*r), H (r*n): last accepted iterate;
+ *   trace[0..n_iter]: rho(k) = e(k)/||X||_F (capacity max_iter+1);
+ *   accepted[k-1], beta_used[k-1], margin[k-1] for k = 1..n_iter, where
+ *   margin = (e(k) - e_compared)/||X||_F; each may be NULL.
+ * Returns ORACLE_OK, ORACLE_EINVAL or ORACLE_ENUMERIC. */
+int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
+                  const double *H0, const oracle_params *p, double *W,
+                  double *H, double *trace, uint8_t *accepted,
+                  double *beta_used, double *margin, int *n_iter);
+
+/* H-side NNLS by HALS: starting from H (r*n, in/out), run `sweeps` sweeps of
+ * the closed-form row updates for min_{H>=0} ||X - W H||_F. */
+int oracle_nnls_h(const oracle_matrix *X, int r, const double *W, double *H,
+                  int sweeps);
+
+/* W-side NNLS by HALS: W (m*r, in/out), H fixed. */
+int oracle_nnls_w(const oracle_matrix *X, int r, const double *H, double *W,
+                  int sweeps);
+
+/* Alg. 3 run on a scripted sequence of outcomes: decreased[k-1] for
+ * k = 1..count. Writes the beta used in iteration k and the upper bound
+ * after iteration k. */
+void oracle_beta_script(int count, const uint8_t *decreased, double beta0,
+                        double gamma, double gamma_bar, double eta, int flags,
+                        double *beta_used, double *betabar_after);
+
+/* ||X - W H||_F / ||X||_F, explicit. */
+double oracle_rel_error(const oracle_matrix *X, int r, const double *W,
+                        const double *H);
+
+/* The same quantity by the identity of Remark 1. */
+double oracle_rel_error_remark1(const oracle_matrix *X, int r, const double *W,
+                                const double *H);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
