@@ -1,0 +1,186 @@
+"""Benchmark of the E-A-HALS outer iteration on one MI355X.
+
+One step = one outer iteration of Algorithm 2 (both X-streaming products,
+both HALS sweep blocks with their epilogues, the FP64 decision). The default
+workload is the planted dense 16384 x 16384, r = 64 problem (X = W H +
+1e-3 |N(0,1)|, seeded); X, W and H are resident in HBM before timing starts.
+
+Prints one JSON line. `value` is outer iterations per second. `roofline`
+covers the dominant kernel (the X-streaming product; both products of an
+iteration are launches of that kernel), timed with HIP events on the stream
+the library launches it on. `cpu_baseline` times the FP64 oracle on a
+bounded sample of the same workload and scales it by the iteration's flop
+count to the full size.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "E-A-HALS iters/s + HBM GB/s at 16384² r=64; batched solves/s, p99 latency"
+HBM_PEAK_GBS = 8000.0
+PRODUCT_SOURCES = ["paper_1805_06604_amd/csrc/kernels_dense.hip",
+                   "paper_1805_06604_amd/csrc/prod_mfma.h"]
+XBYTES = {"f32": 4, "bf16": 2, "f16": 2}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--m", type=int, default=16384)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--r", type=int, default=64)
+    ap.add_argument("--inner-k", type=int, default=10)
+    ap.add_argument("--x-dtype", choices=list(XBYTES), default="f32")
+    ap.add_argument("--prod", choices=["auto", "valu", "exact", "fast"], default="auto")
+    ap.add_argument("--profile-iters", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=2048,
+                    help="m = n of the oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    return ap.parse_args()
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for rel in PRODUCT_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key):
+    """HBM bytes per product launch from the committed counter summary, if it
+    was taken on the current product kernel source for this workload."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(workload_key)
+    if not rec or rec.get("source_sha") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def oracle_flops(m, n, r, K):
+    """Flops of one oracle iteration: two products and the explicit residual
+    (2mnr each) plus the sweeps and Grams."""
+    return 6.0 * m * n * r + 2.0 * (K + 1) * (m + n) * r * r
+
+
+def cpu_baseline(args):
+    import nmf_synth as S
+    import oracle
+    s = args.cpu_sample
+    p = S.planted(0, m=s, n=s, r=args.r)
+    kw = dict(hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
+              inner_k=args.inner_k)
+    t0 = time.perf_counter()
+    oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=args.cpu_iters, **kw)
+    t = time.perf_counter() - t0
+    scale = oracle_flops(args.m, args.n, args.r, args.inner_k) / oracle_flops(s, s, args.r, args.inner_k)
+    per_iter_full = t / args.cpu_iters * scale
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": 1.0 / per_iter_full, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle (single thread), {args.cpu_iters} iterations of the planted "
+                       f"workload at {s}x{s}, r={args.r}, K={args.inner_k} took {t:.2f} s; scaled "
+                       f"to {args.m}x{args.n} by the flop ratio {scale:.1f}; host {cpu}, "
+                       f"os.cpu_count()={os.cpu_count()}")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import nmf_synth as S
+    import paper_1805_06604_amd as P
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    m, n, r, K = args.m, args.n, args.r, args.inner_k
+    p = S.planted(0, m=m, n=n, r=r)
+    total = args.warmup + args.steps + args.profile_iters
+    xd = {"f32": P.XDtype.F32, "bf16": P.XDtype.BF16, "f16": P.XDtype.F16}[args.x_dtype]
+    pm = {"auto": P.Prod.AUTO, "valu": P.Prod.VALU, "exact": P.Prod.MFMA_EXACT,
+          "fast": P.Prod.MFMA_FAST}[args.prod]
+    solver = P.Solver(p.X, r, hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
+                      inner_k=K, max_iter=total, x_dtype=xd, prod=pm)
+    del p
+    W0, H0 = S.init_factors(m, n, r, 0)
+    solver.start(W0, H0, stream=stream)
+    solver.iterate(args.warmup, stream=stream)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    solver.iterate(args.steps, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ms_step = ms / args.steps
+
+    phases = solver.profile(args.profile_iters, stream=stream)
+    res = solver.read(stream=stream)
+    solver.close()
+
+    sx = XBYTES[args.x_dtype]
+    prod_bytes = m * n * sx + (m + n) * r * 4
+    prod_ms = 0.5 * (phases["prod_xt_w"] + phases["prod_x_h"])
+    achieved = prod_bytes / (prod_ms * 1e-3) / 1e9
+    iter_bytes = 2 * m * n * sx + 7 * (m + n) * r * 4
+    key = f"planted_{m}x{n}_r{r}_{args.x_dtype}_{args.prod}"
+    traffic = measured_traffic(key)
+    out = {
+        "metric": METRIC,
+        "value": args.steps / (ms * 1e-3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "bf16": "bf16", "f16": "f16"}[args.x_dtype],
+        "data": "synthetic",
+        "config": {"workload": f"planted dense {m}x{n} r={r}, X = WH + 1e-3|N(0,1)| (seed 0)",
+                   "m": m, "n": n, "r": r, "x_dtype": args.x_dtype, "prod": args.prod,
+                   "inner_k": K, "hp": 3, "beta0": 0.5, "gamma": 1.01, "gamma_bar": 1.005,
+                   "eta": 1.5},
+        "hbm_gbs": iter_bytes * args.steps / (ms * 1e-3) / 1e9,
+        "phase_ms": phases,
+        "rho_final": float(res.trace[-1]),
+        "accepted": int(res.accepted.sum()),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "X-streaming product",
+                     "bytes_per_launch": prod_bytes, "ms_per_launch": prod_ms},
+    }
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

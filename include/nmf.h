@@ -1,0 +1,175 @@
+/*
+ * nmf.h -- C ABI of the MI355X (gfx950) E-A-HALS library.
+ *
+ * Problem (Ang & Gillis, arXiv 1805.06604, Eq. (1)):
+ *     min ||X - W H||_F^2  over  W in R^{m x r}, H in R^{r x n},  W, H >= 0,
+ * solved by Algorithm 2 (extrapolated two-block NMF) around accelerated HALS
+ * (section 1: repeated closed-form row updates of H and column updates of W),
+ * with the beta / beta-bar growth-and-restart rule of Algorithm 3 and the
+ * error of Remark 1. Every outer iteration runs on the GPU; the host only
+ * enqueues work.
+ *
+ * Conventions
+ *   - Host matrices are row-major: X is m x n, W is m x r, H is r x n.
+ *   - Every entry point returns nmf_status; no C++ exception crosses the ABI.
+ *   - Arguments are validated before any device work; on an error no output
+ *     is written and nmf_last_error() describes it.
+ *   - A context is bound to the device that was current at nmf_create and is
+ *     not thread-safe: use one per thread.
+ *   - Streams are passed as `void *` holding a hipStream_t (NULL = the null
+ *     stream).
+ */
+#ifndef NMF_H
+#define NMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmf_ctx nmf_ctx;
+
+typedef enum {
+    NMF_OK = 0,
+    NMF_E_INVAL = 1,        /* an argument is out of its documented domain   */
+    NMF_E_UNSUPPORTED = 2,  /* valid, but not provided by this build         */
+    NMF_E_NOMEM = 3,        /* host or device allocation failed              */
+    NMF_E_DEVICE = 4,       /* a HIP call failed                             */
+    NMF_E_NUMERIC = 5,      /* the initial error e(0) is not finite          */
+    NMF_E_STATE = 6         /* call out of order (e.g. nmf_iterate before
+                               nmf_start)                                    */
+} nmf_status;
+
+typedef enum { NMF_DENSE_ROWMAJOR = 0, NMF_CSR = 1 } nmf_format;
+
+/* Storage type of X on the device. Products accumulate in FP32 and the
+ * objective combination runs in FP64 whatever this is. */
+typedef enum { NMF_X_F32 = 0, NMF_X_BF16 = 1, NMF_X_F16 = 2 } nmf_xdtype;
+
+/* Inner rule of A-HALS (section 1: the rows of H are updated several times
+ * before W, reusing W^T W and W^T X). FIXED runs inner_k sweeps per block. */
+typedef enum { NMF_INNER_FIXED = 0 } nmf_inner;
+
+/* How the two O(mnr) products X^T W and X H^T are computed. Whatever the
+ * choice, the products are summed over K-chunks in FP64, and the HALS sweeps,
+ * Grams and objective run in FP64 on FP32-stored W and H.
+ *   AUTO       : MFMA_EXACT for FP32 X, MFMA_FAST for BF16 and FP16 X.
+ *   VALU       : FP64 FMA on the vector ALUs (exact products of the stored
+ *                values, FP64 sums): the reference-accuracy path, slowest.
+ *   MFMA_EXACT : matrix cores. Each FP32 operand is split exactly into three
+ *                BF16 parts of 8 significant bits and every part product of
+ *                relative weight >= 2^-16 is accumulated in FP32 within a
+ *                K-chunk: products as accurate as FP32 arithmetic.
+ *   MFMA_FAST  : matrix cores with operands carried to 16 significant bits
+ *                (part products of weight >= 2^-8). */
+typedef enum {
+    NMF_PROD_AUTO = 0,
+    NMF_PROD_VALU = 1,
+    NMF_PROD_MFMA_EXACT = 2,
+    NMF_PROD_MFMA_FAST = 3
+} nmf_prod;
+
+/* Flags selecting the alternative readings of Algorithm 3 / Algorithm 2. */
+#define NMF_FLAG_BETABAR_LAST_ACCEPTED 1  /* on a restart the upper bound becomes
+                                             the beta of the last accepted
+                                             iteration instead of beta_{k-1} */
+#define NMF_FLAG_CMP_LAST_ACCEPTED 2      /* compare e(k) with the last
+                                             accepted error instead of the
+                                             previous computed one          */
+
+/* Input matrix (host memory; nmf_create copies it). */
+typedef struct {
+    int32_t fmt;                /* nmf_format                                   */
+    int64_t m, n;               /* rows, columns; both >= 1                     */
+    const float *dense;         /* DENSE: m*n row-major                         */
+    const int64_t *row_ptr;     /* CSR: m+1 offsets, row_ptr[0] = 0             */
+    const int32_t *col_idx;     /* CSR: column indices, strictly increasing per row */
+    const float *val;           /* CSR: nnz values                              */
+    int64_t nnz;                /* CSR: row_ptr[m]                              */
+} nmf_matrix;
+
+/* Parameters (Algorithm 2 and 3). nmf_params_default() fills the values of
+ * section 5.3.2 for E-A-HALS: hp 3, beta0 0.5, eta 1.5, gamma 1.01,
+ * gamma_bar 1.005, 10 inner sweeps, 100 iterations, FP32 X. */
+typedef struct {
+    int32_t r;                  /* rank, 1..64                                  */
+    int32_t hp;                 /* 1, 2 or 3 (Algorithm 2)                      */
+    double beta0;               /* beta of iteration 1, in [0, 1); 0 = A-HALS   */
+    double gamma, gamma_bar, eta; /* 1 < gamma_bar < gamma < eta (Algorithm 3)  */
+    int32_t inner_rule;         /* nmf_inner                                    */
+    int32_t inner_k;            /* sweeps per block update, 1..1000             */
+    int32_t max_iter;           /* outer iterations, >= 0                       */
+    double tol;                 /* > 0: stop after an accepted iteration whose
+                                   relative error moved by less than tol        */
+    int32_t x_dtype;            /* nmf_xdtype                                   */
+    int32_t prod;               /* nmf_prod                                     */
+    int32_t flags;              /* NMF_FLAG_*                                   */
+} nmf_params;
+
+void nmf_params_default(nmf_params *p);
+
+/* Validates X and p, uploads X (and the transposed copy the second product
+ * streams), converts it to x_dtype and computes ||X||_F^2 in FP64 from the
+ * given FP32 values. X may be freed once this returns.
+ * Errors: NMF_E_INVAL (shape, malformed CSR, non-finite X, all-zero X, any
+ * parameter out of domain), NMF_E_UNSUPPORTED (r > 64), NMF_E_NOMEM,
+ * NMF_E_DEVICE. On error *out is NULL. */
+nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out);
+
+/* Synchronous solve (Algorithm 2, first step through max_iter iterations).
+ * W0 (m*r) and H0 (r*n) are host arrays, finite and >= 0. Outputs, caller
+ * allocated host arrays: W (m*r), H (r*n) = the last accepted iterate;
+ * trace[0..*n_iter] = ||X - W_n H_y||_F / ||X||_F per iteration (trace[0]
+ * is the initial error), trace_cap >= max_iter + 1; accepted and beta
+ * (nullable) receive, for k = 1..*n_iter, 1 for an accepted iteration and 0
+ * for a restart, and the beta used in iteration k.
+ * Errors: NMF_E_INVAL (null or non-finite / negative W0 or H0, small
+ * trace_cap), NMF_E_NUMERIC (e(0) not finite), NMF_E_DEVICE. */
+nmf_status nmf_solve(nmf_ctx *ctx, const float *W0, const float *H0, float *W,
+                     float *H, double *trace, int32_t trace_cap,
+                     int32_t *n_iter, uint8_t *accepted, double *beta);
+
+/* Asynchronous interface for callers that own device memory and streams.
+ *
+ * nmf_start: loads W0 (m*r) and H0 (r*n), from the host (on_device = 0) or
+ * from device memory (on_device = 1), resets the beta state and enqueues the
+ * computation of e(0) on `stream`. It synchronizes `stream` once to check the
+ * inputs and e(0). Errors as for nmf_solve.
+ *
+ * nmf_iterate: enqueues `iters` outer iterations on `stream` and returns
+ * without waiting. Iterations past max_iter, or after the tol stop, do
+ * nothing. Errors: NMF_E_STATE before nmf_start, NMF_E_INVAL for iters < 0.
+ *
+ * nmf_read: waits for `stream`, then copies the last accepted W (m*r) and H
+ * (r*n) into host (on_device = 0) or device (on_device = 1) arrays, and the
+ * trace, decisions and betas into host arrays (each nullable). */
+nmf_status nmf_start(nmf_ctx *ctx, const float *W0, const float *H0,
+                     int32_t on_device, void *stream);
+nmf_status nmf_iterate(nmf_ctx *ctx, int32_t iters, void *stream);
+nmf_status nmf_read(nmf_ctx *ctx, float *W, float *H, int32_t on_device,
+                    double *trace, int32_t trace_cap, int32_t *n_iter,
+                    uint8_t *accepted, double *beta, void *stream);
+
+/* Per-phase timing. Runs `iters` further outer iterations (they advance the
+ * solve like nmf_iterate, within max_iter) launched one kernel at a time on
+ * `stream`, with a HIP event recorded before and after each phase, waits for
+ * them, and writes the average duration in milliseconds of each phase to
+ * ms[0..3]: ms[0] = X^T W_y (first product), ms[1] = H sweeps with their
+ * epilogue, ms[2] = X H_w^T (second product), ms[3] = W sweeps with their
+ * epilogue and the accept/restart decision.
+ * Errors: NMF_E_STATE before nmf_start, NMF_E_INVAL (iters < 1, ms NULL, or
+ * fewer than iters iterations left before max_iter), NMF_E_DEVICE. */
+nmf_status nmf_profile(nmf_ctx *ctx, int32_t iters, void *stream, double *ms);
+
+/* Frees every host and device resource of ctx. NULL is allowed. */
+void nmf_destroy(nmf_ctx *ctx);
+
+/* Message of the last failure on ctx, or of the last failed nmf_create on
+ * this thread when ctx is NULL. Never NULL. */
+const char *nmf_last_error(const nmf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMF_H */

@@ -17,6 +17,7 @@ OK, EINVAL, ENUMERIC, ENOMEM = 0, 1, 2, 3
 BETABAR_LAST_ACCEPTED = 1
 CMP_LAST_ACCEPTED = 2
 ERR_REMARK1 = 4
+ROUND_F32 = 8
 
 _lib = None
 

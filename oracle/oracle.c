@@ -99,14 +99,23 @@ static void gram_rows(int64_t n, int r, const double *H, double *B)
  * other rows fixed (the closed form of section 1):
  *   H(k,:) = max(0, (C(k,:) - sum_{j != k} G(k,j) H(j,:)) / G(k,k)),
  * with C = W^T X and G = W^T W. Rows are visited in ascending k and the
- * updated rows are used at once (Gauss-Seidel). A zero G(k,k) keeps the row
- * (R10). */
+ * updated rows are used at once (Gauss-Seidel). A zero G(k,k) means row k
+ * does not enter the objective: it is only projected onto H(k,:) >= 0 (R10). */
+static void project_row(int64_t len, double *v)
+{
+    for (int64_t i = 0; i < len; ++i)
+        if (!(v[i] >= 0.0)) v[i] = 0.0;
+}
+
 static void hals_rows_h(int64_t n, int r, const double *C, const double *G,
                         double *H)
 {
     for (int k = 0; k < r; ++k) {
         const double d = G[k * r + k];
-        if (!(d > 0.0)) continue;
+        if (!(d > 0.0)) {
+            project_row(n, H + (int64_t)k * n);
+            continue;
+        }
         for (int64_t c = 0; c < n; ++c) {
             double num = C[(int64_t)k * n + c];
             for (int j = 0; j < r; ++j)
@@ -125,7 +134,11 @@ static void hals_cols_w(int64_t m, int r, const double *A, const double *B,
 {
     for (int k = 0; k < r; ++k) {
         const double d = B[k * r + k];
-        if (!(d > 0.0)) continue;
+        if (!(d > 0.0)) {
+            for (int64_t i = 0; i < m; ++i)
+                if (!(W[i * r + k] >= 0.0)) W[i * r + k] = 0.0;
+            continue;
+        }
         for (int64_t i = 0; i < m; ++i) {
             double num = A[i * r + k];
             for (int j = 0; j < r; ++j)
@@ -243,6 +256,14 @@ static int valid_matrix(const oracle_matrix *X)
     return 1;
 }
 
+/* Rounds every entry to the nearest FP32 value (ORACLE_ROUND_F32: models the
+ * storage of the iterates in single precision, nothing else). */
+static void round_f32(int64_t len, double *v, int flags)
+{
+    if (!(flags & ORACLE_ROUND_F32)) return;
+    for (int64_t i = 0; i < len; ++i) v[i] = (double)(float)v[i];
+}
+
 /* Extrapolation: Y = N + beta (N - P), optionally projected onto Y >= 0. */
 static void extrapolate(int64_t len, double beta, const double *N,
                         const double *P, double *Y, int project)
@@ -307,11 +328,13 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         gram_cols(m, r, Wy, G);
         memcpy(Hn, Hy, sizeof(double) * rn);
         for (int s = 0; s < p->inner_k; ++s) hals_rows_h(n, r, C, G, Hn);
+        round_f32(rn, Hn, p->flags);
 
         /* hp >= 2: extrapolate H now (hp = 3: and project). R6: for hp = 1
          * the same H_y is formed after the W update and only warm-starts the
          * next H update; its value does not depend on that placement. */
         extrapolate(rn, beta, Hn, H, Hyn, p->hp == 3);
+        round_f32(rn, Hyn, p->flags);
         const double *Hw = (p->hp == 1) ? Hn : Hyn;
 
         /* W_n: NNLS in W with H_w fixed, warm-started at W_y. */
@@ -319,9 +342,11 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         gram_rows(n, r, Hw, B);
         memcpy(Wn, Wy, sizeof(double) * mr);
         for (int s = 0; s < p->inner_k; ++s) hals_cols_w(m, r, A, B, Wn);
+        round_f32(mr, Wn, p->flags);
 
         /* W_y = W_n + beta (W_n - W). */
         extrapolate(mr, beta, Wn, W, Wyn, 0);
+        round_f32(mr, Wyn, p->flags);
 
         /* e(k) = ||X - W_n H_w||_F. */
         double e2 = (p->flags & ORACLE_ERR_REMARK1)

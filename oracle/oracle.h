@@ -33,7 +33,9 @@
  *   R9  A non-finite e(k) is a restart and does not replace the previous e;
  *       a non-finite e(0) is an error (ORACLE_ENUMERIC).
  *   R10 A HALS coordinate whose denominator ||W(:,k)||^2 (or ||H(k,:)||^2)
- *       is zero keeps its value; rows/columns are visited in ascending k.
+ *       is zero does not enter the objective: it is only projected onto
+ *       [0, inf) (kept when already >= 0; the warm start may be negative).
+ *       Rows/columns are visited in ascending k.
  *   R11 The output is the last accepted (W, H).
  *   R12 tol > 0 stops after an accepted iteration k with
  *       |rho(k) - rho(k-1)| < tol; rho = e / ||X||_F.
@@ -56,6 +58,9 @@ extern "C" {
 #define ORACLE_BETABAR_LAST_ACCEPTED 1  /* R5 alternative */
 #define ORACLE_CMP_LAST_ACCEPTED     2  /* R7 alternative */
 #define ORACLE_ERR_REMARK1           4  /* e(k) by Remark 1 instead of the explicit residual */
+#define ORACLE_ROUND_F32             8  /* round the stored iterates W_n, H_n, W_y, H_y
+                                           to FP32 after each update (conditioning
+                                           probe; all arithmetic stays FP64)       */
 
 typedef struct {
     int64_t m, n;

@@ -1,0 +1,277 @@
+"""ctypes binding of libnmf.so (the C ABI declared in include/nmf.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Host arrays are numpy; device arrays are torch CUDA tensors (torch supplies
+device memory and streams, nothing else). The library must be built
+(``__graft_entry__.build()``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import enum
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnmf.so")
+
+EXPORTS = ("nmf_params_default", "nmf_create", "nmf_solve", "nmf_start",
+           "nmf_iterate", "nmf_read", "nmf_profile", "nmf_destroy",
+           "nmf_last_error")
+
+
+class Status(enum.IntEnum):
+    OK = 0
+    E_INVAL = 1
+    E_UNSUPPORTED = 2
+    E_NOMEM = 3
+    E_DEVICE = 4
+    E_NUMERIC = 5
+    E_STATE = 6
+
+
+class Format(enum.IntEnum):
+    DENSE = 0
+    CSR = 1
+
+
+class XDtype(enum.IntEnum):
+    F32 = 0
+    BF16 = 1
+    F16 = 2
+
+
+class Prod(enum.IntEnum):
+    AUTO = 0
+    VALU = 1
+    MFMA_EXACT = 2
+    MFMA_FAST = 3
+
+
+FLAG_BETABAR_LAST_ACCEPTED = 1
+FLAG_CMP_LAST_ACCEPTED = 2
+
+
+class NMFError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = Status(status)
+        super().__init__(f"{self.status.name}: {message}")
+
+
+class _Matrix(C.Structure):
+    _fields_ = [("fmt", C.c_int32), ("m", C.c_int64), ("n", C.c_int64),
+                ("dense", C.c_void_p), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("nnz", C.c_int64)]
+
+
+class Params(C.Structure):
+    _fields_ = [("r", C.c_int32), ("hp", C.c_int32), ("beta0", C.c_double),
+                ("gamma", C.c_double), ("gamma_bar", C.c_double),
+                ("eta", C.c_double), ("inner_rule", C.c_int32),
+                ("inner_k", C.c_int32), ("max_iter", C.c_int32),
+                ("tol", C.c_double), ("x_dtype", C.c_int32),
+                ("prod", C.c_int32), ("flags", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libnmf.so once; raises if it has not been built.
+
+    torch is imported first when it is installed: libnmf.so then binds to the
+    HIP runtime torch brings (one runtime per process), so that torch tensors
+    and streams handed to the library belong to the same runtime."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build()")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        p, i32 = C.c_void_p, C.c_int32
+        L.nmf_params_default.argtypes = [p]
+        L.nmf_params_default.restype = None
+        L.nmf_create.argtypes = [p, p, p]
+        L.nmf_create.restype = i32
+        L.nmf_solve.argtypes = [p, p, p, p, p, p, i32, p, p, p]
+        L.nmf_solve.restype = i32
+        L.nmf_start.argtypes = [p, p, p, i32, p]
+        L.nmf_start.restype = i32
+        L.nmf_iterate.argtypes = [p, i32, p]
+        L.nmf_iterate.restype = i32
+        L.nmf_read.argtypes = [p, p, p, i32, p, i32, p, p, p, p]
+        L.nmf_read.restype = i32
+        L.nmf_profile.argtypes = [p, i32, p, p]
+        L.nmf_profile.restype = i32
+        L.nmf_destroy.argtypes = [p]
+        L.nmf_destroy.restype = None
+        L.nmf_last_error.argtypes = [p]
+        L.nmf_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def make_params(r, **kw) -> Params:
+    prm = Params()
+    lib().nmf_params_default(C.byref(prm))
+    prm.r = r
+    for k, v in kw.items():
+        if not hasattr(prm, k):
+            raise TypeError(f"unknown parameter {k!r}")
+        setattr(prm, k, int(v) if isinstance(v, (enum.IntEnum, bool)) else v)
+    return prm
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+@dataclasses.dataclass
+class Result:
+    W: np.ndarray
+    H: np.ndarray
+    trace: np.ndarray
+    accepted: np.ndarray
+    beta: np.ndarray
+    n_iter: int
+
+
+class Solver:
+    """One context: X resident on the current GPU, reusable for many solves.
+
+    ``X`` is a float32 (m, n) numpy array, or an object with ``m, n,
+    row_ptr, col_idx, val`` (CSR). Keyword arguments set nmf_params fields
+    (hp, beta0, gamma, gamma_bar, eta, inner_k, max_iter, tol, x_dtype,
+    prod, flags)."""
+
+    def __init__(self, X, r, **params):
+        self._ctx = C.c_void_p()
+        self.params = make_params(r, **params)
+        mat = _Matrix()
+        keep = []
+        if hasattr(X, "row_ptr"):
+            rp = np.ascontiguousarray(X.row_ptr, dtype=np.int64)
+            ci = np.ascontiguousarray(X.col_idx, dtype=np.int32)
+            va = np.ascontiguousarray(X.val, dtype=np.float32)
+            keep += [rp, ci, va]
+            mat.fmt, mat.m, mat.n = Format.CSR, X.m, X.n
+            mat.row_ptr, mat.col_idx, mat.val = rp.ctypes.data, ci.ctypes.data, va.ctypes.data
+            mat.nnz = int(rp[-1])
+        else:
+            Xd = np.ascontiguousarray(X, dtype=np.float32)
+            keep.append(Xd)
+            mat.fmt, (mat.m, mat.n) = Format.DENSE, Xd.shape
+            mat.dense = Xd.ctypes.data
+        self.m, self.n, self.r = int(mat.m), int(mat.n), int(r)
+        st = lib().nmf_create(C.byref(mat), C.byref(self.params), C.byref(self._ctx))
+        if st != Status.OK:
+            raise NMFError(st, lib().nmf_last_error(None).decode())
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, st):
+        if st != Status.OK:
+            raise NMFError(st, lib().nmf_last_error(self._ctx).decode())
+
+    def close(self):
+        if self._ctx:
+            lib().nmf_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------- entry points
+    def solve(self, W0, H0) -> Result:
+        """nmf_solve: host in, host out, synchronous."""
+        W0 = np.ascontiguousarray(W0, dtype=np.float32)
+        H0 = np.ascontiguousarray(H0, dtype=np.float32)
+        if W0.shape != (self.m, self.r) or H0.shape != (self.r, self.n):
+            raise ValueError("W0 must be (m, r) and H0 (r, n)")
+        cap = self.params.max_iter + 1
+        W = np.empty((self.m, self.r), np.float32)
+        H = np.empty((self.r, self.n), np.float32)
+        trace = np.zeros(cap)
+        acc = np.zeros(max(cap - 1, 1), np.uint8)
+        beta = np.zeros(max(cap - 1, 1))
+        nit = C.c_int32()
+        self._check(lib().nmf_solve(self._ctx, _ptr(W0), _ptr(H0), _ptr(W), _ptr(H),
+                                    _ptr(trace), cap, C.byref(nit), _ptr(acc),
+                                    _ptr(beta)))
+        k = nit.value
+        return Result(W, H, trace[:k + 1], acc[:k].astype(bool), beta[:k], k)
+
+    def start(self, W0, H0, stream=None):
+        """nmf_start from numpy (host) or torch CUDA tensors (device)."""
+        if hasattr(W0, "data_ptr"):
+            if tuple(W0.shape) != (self.m, self.r) or tuple(H0.shape) != (self.r, self.n):
+                raise ValueError("W0 must be (m, r) and H0 (r, n)")
+            if not (W0.is_contiguous() and H0.is_contiguous()):
+                raise ValueError("device W0 and H0 must be contiguous float32")
+            self._check(lib().nmf_start(self._ctx, C.c_void_p(W0.data_ptr()),
+                                        C.c_void_p(H0.data_ptr()), 1, _stream(stream)))
+        else:
+            W0 = np.ascontiguousarray(W0, dtype=np.float32)
+            H0 = np.ascontiguousarray(H0, dtype=np.float32)
+            if W0.shape != (self.m, self.r) or H0.shape != (self.r, self.n):
+                raise ValueError("W0 must be (m, r) and H0 (r, n)")
+            self._check(lib().nmf_start(self._ctx, _ptr(W0), _ptr(H0), 0, _stream(stream)))
+
+    def iterate(self, iters, stream=None):
+        self._check(lib().nmf_iterate(self._ctx, int(iters), _stream(stream)))
+
+    def profile(self, iters, stream=None):
+        """nmf_profile: average ms of the four phases over `iters` eager
+        iterations (products, H sweeps, W sweeps + decision)."""
+        ms = np.zeros(4)
+        self._check(lib().nmf_profile(self._ctx, int(iters), _stream(stream), _ptr(ms)))
+        return dict(prod_xt_w=ms[0], sweep_h=ms[1], prod_x_h=ms[2], sweep_w=ms[3])
+
+    def read(self, W=None, H=None, stream=None) -> Result:
+        """nmf_read into host arrays, or into given torch CUDA tensors."""
+        cap = self.params.max_iter + 1
+        trace = np.zeros(cap)
+        acc = np.zeros(max(cap - 1, 1), np.uint8)
+        beta = np.zeros(max(cap - 1, 1))
+        nit = C.c_int32()
+        if W is not None and hasattr(W, "data_ptr"):
+            self._check(lib().nmf_read(self._ctx, C.c_void_p(W.data_ptr()),
+                                       C.c_void_p(H.data_ptr()), 1, _ptr(trace), cap,
+                                       C.byref(nit), _ptr(acc), _ptr(beta), _stream(stream)))
+            Wout, Hout = W, H
+        else:
+            Wout = np.empty((self.m, self.r), np.float32)
+            Hout = np.empty((self.r, self.n), np.float32)
+            self._check(lib().nmf_read(self._ctx, _ptr(Wout), _ptr(Hout), 0, _ptr(trace),
+                                       cap, C.byref(nit), _ptr(acc), _ptr(beta),
+                                       _stream(stream)))
+        k = nit.value
+        return Result(Wout, Hout, trace[:k + 1], acc[:k].astype(bool), beta[:k], k)
+
+
+def solve(X, r, W0, H0, **params) -> Result:
+    """One-shot solve: create a context, run nmf_solve, destroy it."""
+    with Solver(X, r, **params) as s:
+        return s.solve(W0, H0)

@@ -1,0 +1,524 @@
+// Host engine and C ABI (include/nmf.h): validation, device buffers, the
+// hipGraph of one outer iteration of Algorithm 2, and the entry points.
+#include "nmf.h"
+#include "nmf_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using nmf::Buffers;
+using nmf::DevState;
+
+struct nmf_ctx {
+    int device = 0;
+    nmf_params p{};
+    int64_t m = 0, n = 0;
+    int r = 0, rp = 0;
+    int fmt = NMF_DENSE_ROWMAJOR;
+    void *X = nullptr;   // m_pad x ldx, storage dtype, zero padding
+    void *Xt = nullptr;  // n_pad x ldxt
+    int64_t ldx = 0, ldxt = 0;
+    int prod_kernel = nmf::PK_MFMA_L2;
+    nmf::ProdArgs pa{};  // A = X H_w^T
+    nmf::ProdArgs pc{};  // C^T = X^T W_y
+    double nx2 = 0.0;
+    Buffers b;
+    hipStream_t own = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool started = false;
+    int32_t launched = 0;
+    DevState hs{};       // host copy of the device state
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+nmf_status fail(nmf_ctx *ctx, nmf_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(ctx, call)                                                          \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return fail(ctx, NMF_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t xbytes(int xdtype) { return xdtype == NMF_X_F32 ? 4 : 2; }
+
+int round_rank(int r) { return ((r + 15) / 16) * 16; }
+
+int64_t round_up(int64_t v, int64_t q) { return ((v + q - 1) / q) * q; }
+
+int choose_kernel(const nmf_params *p)
+{
+    switch (p->prod) {
+    case NMF_PROD_VALU: return nmf::PK_VALU;
+    case NMF_PROD_MFMA_EXACT: return nmf::PK_MFMA_L2;
+    case NMF_PROD_MFMA_FAST: return nmf::PK_MFMA_L1;
+    default: return p->x_dtype == NMF_X_F32 ? nmf::PK_MFMA_L2 : nmf::PK_MFMA_L1;
+    }
+}
+
+// Split-K plan of one product: enough workgroups to fill the chip (about 512
+// of 128 rows each), K-chunks of whole 64-column tiles.
+void plan_product(nmf::ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, int64_t K,
+                  int64_t ld)
+{
+    a.rows = rows;
+    a.rows_pad = rows_pad;
+    a.K = K;
+    a.ld = ld;
+    if (kernel == nmf::PK_VALU) {
+        a.nsplit = 1;
+        a.kchunk = ld;
+        return;
+    }
+    const int64_t rb = rows_pad / 128, tiles = ld / 64;
+    int64_t want = (512 + rb - 1) / rb;
+    want = std::max<int64_t>(1, std::min<int64_t>({want, tiles, 32}));
+    a.kchunk = ((tiles + want - 1) / want) * 64;
+    a.nsplit = (int)((ld + a.kchunk - 1) / a.kchunk);
+}
+
+nmf_status check_params(const nmf_params *p)
+{
+    if (!p) return fail(nullptr, NMF_E_INVAL, "params is NULL");
+    if (p->r < 1) return fail(nullptr, NMF_E_INVAL, "r = %d must be >= 1", p->r);
+    if (p->r > 64) return fail(nullptr, NMF_E_UNSUPPORTED, "r = %d: ranks above 64 are not provided", p->r);
+    if (p->hp < 1 || p->hp > 3) return fail(nullptr, NMF_E_INVAL, "hp = %d must be 1, 2 or 3", p->hp);
+    if (!(p->beta0 >= 0.0 && p->beta0 < 1.0))
+        return fail(nullptr, NMF_E_INVAL, "beta0 = %g must lie in [0, 1)", p->beta0);
+    if (!(1.0 < p->gamma_bar && p->gamma_bar < p->gamma && p->gamma < p->eta) ||
+        !std::isfinite(p->eta))
+        return fail(nullptr, NMF_E_INVAL,
+                    "need 1 < gamma_bar < gamma < eta (got %g, %g, %g)", p->gamma_bar,
+                    p->gamma, p->eta);
+    if (p->inner_rule != NMF_INNER_FIXED)
+        return fail(nullptr, NMF_E_UNSUPPORTED, "inner_rule %d is not provided", p->inner_rule);
+    if (p->inner_k < 1 || p->inner_k > 1000)
+        return fail(nullptr, NMF_E_INVAL, "inner_k = %d must lie in 1..1000", p->inner_k);
+    if (p->max_iter < 0 || p->max_iter > (1 << 28))
+        return fail(nullptr, NMF_E_INVAL, "max_iter = %d out of range", p->max_iter);
+    if (!(p->tol >= 0.0) || !std::isfinite(p->tol))
+        return fail(nullptr, NMF_E_INVAL, "tol = %g must be finite and >= 0", p->tol);
+    if (p->x_dtype < NMF_X_F32 || p->x_dtype > NMF_X_F16)
+        return fail(nullptr, NMF_E_INVAL, "x_dtype = %d unknown", p->x_dtype);
+    if (p->prod < NMF_PROD_AUTO || p->prod > NMF_PROD_MFMA_FAST)
+        return fail(nullptr, NMF_E_INVAL, "prod = %d unknown", p->prod);
+    if (p->flags & ~(NMF_FLAG_BETABAR_LAST_ACCEPTED | NMF_FLAG_CMP_LAST_ACCEPTED))
+        return fail(nullptr, NMF_E_INVAL, "unknown flags 0x%x", p->flags);
+    return NMF_OK;
+}
+
+nmf_status check_matrix(const nmf_matrix *X)
+{
+    if (!X) return fail(nullptr, NMF_E_INVAL, "X is NULL");
+    if (X->m < 1 || X->n < 1)
+        return fail(nullptr, NMF_E_INVAL, "X is %lld x %lld; both must be >= 1",
+                    (long long)X->m, (long long)X->n);
+    if (X->m > (int64_t)1 << 31 || X->n > (int64_t)1 << 31)
+        return fail(nullptr, NMF_E_UNSUPPORTED, "X dimensions above 2^31 are not provided");
+    if (X->fmt == NMF_DENSE_ROWMAJOR) {
+        if (!X->dense) return fail(nullptr, NMF_E_INVAL, "dense X has a NULL pointer");
+        const int64_t cnt = X->m * X->n;
+        for (int64_t i = 0; i < cnt; ++i)
+            if (!std::isfinite(X->dense[i]))
+                return fail(nullptr, NMF_E_INVAL, "X has a non-finite entry at %lld", (long long)i);
+        return NMF_OK;
+    }
+    if (X->fmt == NMF_CSR)
+        return fail(nullptr, NMF_E_UNSUPPORTED, "CSR input is not provided by this build");
+    return fail(nullptr, NMF_E_INVAL, "fmt = %d unknown", X->fmt);
+}
+
+void free_all(nmf_ctx *c)
+{
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    void *ptrs[] = {c->X, c->Xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH, c->b.A, c->b.Ct,
+                    c->b.part_g, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
+                    c->b.accepted, c->b.beta_used, c->b.stage};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->own) (void)hipStreamDestroy(c->own);
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    return hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(count, 1) * sizeof(T));
+}
+
+nmf_status alloc_buffers(nmf_ctx *c)
+{
+    const int rp = c->rp;
+    const int64_t m = c->m, n = c->n;
+    const int gs = nmf::gram_stride(rp);
+    const int64_t nblk = (std::max(m, n) + nmf::kRowsPerBlock - 1) / nmf::kRowsPerBlock;
+    Buffers &b = c->b;
+    HIP_TRY(c, dalloc(&b.Wf, (size_t)nmf::kSlots * m * rp));
+    HIP_TRY(c, dalloc(&b.Hf, (size_t)nmf::kSlots * n * rp));
+    HIP_TRY(c, dalloc(&b.GW, (size_t)nmf::kSlots * gs));
+    HIP_TRY(c, dalloc(&b.GH, (size_t)gs));
+    HIP_TRY(c, dalloc(&b.A, (size_t)c->pa.nsplit * b.m_pad * rp));
+    HIP_TRY(c, dalloc(&b.Ct, (size_t)c->pc.nsplit * b.n_pad * rp));
+    c->pa.Y = b.A;
+    c->pc.Y = b.Ct;
+    HIP_TRY(c, dalloc(&b.part_g, (size_t)nblk * 2 * rp * rp));
+    HIP_TRY(c, dalloc(&b.part_d, (size_t)std::max<int64_t>(nblk * 2, 1024)));
+    HIP_TRY(c, dalloc(&b.counters, (size_t)nmf::CNT_N));
+    HIP_TRY(c, hipMemset(b.counters, 0, sizeof(uint32_t) * nmf::CNT_N));
+    HIP_TRY(c, dalloc(&b.st, 1));
+    HIP_TRY(c, dalloc(&b.trace, (size_t)c->p.max_iter + 1));
+    HIP_TRY(c, dalloc(&b.accepted, (size_t)c->p.max_iter));
+    HIP_TRY(c, dalloc(&b.beta_used, (size_t)c->p.max_iter));
+    HIP_TRY(c, dalloc(&b.stage, (size_t)(m + n) * c->r));
+    // Zero the factor slots once so that no slot ever holds garbage padding.
+    HIP_TRY(c, hipMemset(b.Wf, 0, sizeof(float) * nmf::kSlots * m * rp));
+    HIP_TRY(c, hipMemset(b.Hf, 0, sizeof(float) * nmf::kSlots * n * rp));
+    return NMF_OK;
+}
+
+nmf_status upload_dense(nmf_ctx *c, const nmf_matrix *X)
+{
+    const int64_t cnt = c->m * c->n;
+    const int xd = c->p.x_dtype;
+    const size_t xsz = (size_t)c->b.m_pad * c->ldx * xbytes(xd);
+    const size_t xtsz = (size_t)c->b.n_pad * c->ldxt * xbytes(xd);
+    HIP_TRY(c, hipMalloc(&c->X, xsz));
+    HIP_TRY(c, hipMalloc(&c->Xt, xtsz));
+    HIP_TRY(c, hipMemset(c->X, 0, xsz));
+    HIP_TRY(c, hipMemset(c->Xt, 0, xtsz));
+    float *src = nullptr;
+    HIP_TRY(c, dalloc(&src, (size_t)cnt));
+    hipError_t e = hipMemcpy(src, X->dense, sizeof(float) * cnt, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = nmf::launch_convert_x(src, c->m, c->n, xd, c->X, c->ldx, c->Xt, c->ldxt, c->own);
+    double *nx2 = nullptr;
+    if (e == hipSuccess) e = dalloc(&nx2, 1);
+    if (e == hipSuccess)
+        e = nmf::launch_sumsq_typed(c->X, xd, (int64_t)(xsz / xbytes(xd)), c->b.part_d, 1024, nx2,
+                                    c->own);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->own);
+    if (e == hipSuccess) e = hipMemcpy(&c->nx2, nx2, sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(src);
+    if (nx2) (void)hipFree(nx2);
+    if (e != hipSuccess)
+        return fail(c, NMF_E_DEVICE, "uploading X failed: %s", hipGetErrorString(e));
+    return NMF_OK;
+}
+
+// One outer iteration as four launches. With `ev` non-null, event ev[i] is
+// recorded before phase i and ev[4] after the last one.
+nmf_status enqueue_iteration(nmf_ctx *c, hipStream_t s, hipEvent_t *ev = nullptr)
+{
+    const int rp = c->rp, xd = c->p.x_dtype, pk = c->prod_kernel;
+    Buffers &b = c->b;
+    // a1: C^T = X^T W_y ; a2-a4: H sweeps + epilogue ; a5: A = X H_w^T ;
+    // a6-a8: W sweeps + epilogue + decision.
+    if (ev) HIP_TRY(c, hipEventRecord(ev[0], s));
+    HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pc, s));
+    if (ev) HIP_TRY(c, hipEventRecord(ev[1], s));
+    HIP_TRY(c, nmf::launch_sweep_h(rp, c->n, c->r, c->p.inner_k, b, c->m, s));
+    if (ev) HIP_TRY(c, hipEventRecord(ev[2], s));
+    HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pa, s));
+    if (ev) HIP_TRY(c, hipEventRecord(ev[3], s));
+    HIP_TRY(c, nmf::launch_sweep_w(rp, c->m, c->r, c->p.inner_k, b, c->n, s));
+    if (ev) HIP_TRY(c, hipEventRecord(ev[4], s));
+    return NMF_OK;
+}
+
+nmf_status build_graph(nmf_ctx *c)
+{
+    HIP_TRY(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
+    nmf_status st = enqueue_iteration(c, c->own);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->own, &g);
+    if (st != NMF_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(c, NMF_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    c->graph = g;
+    HIP_TRY(c, hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0));
+    return NMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void nmf_params_default(nmf_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->r = 10;
+    p->hp = 3;
+    p->beta0 = 0.5;
+    p->gamma = 1.01;
+    p->gamma_bar = 1.005;
+    p->eta = 1.5;
+    p->inner_rule = NMF_INNER_FIXED;
+    p->inner_k = 10;
+    p->max_iter = 100;
+    p->tol = 0.0;
+    p->x_dtype = NMF_X_F32;
+    p->prod = NMF_PROD_AUTO;
+    p->flags = 0;
+}
+
+nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
+{
+    if (!out) return fail(nullptr, NMF_E_INVAL, "out is NULL");
+    *out = nullptr;
+    nmf_status st = check_params(p);
+    if (st != NMF_OK) return st;
+    st = check_matrix(X);
+    if (st != NMF_OK) return st;
+
+    nmf_ctx *c = new (std::nothrow) nmf_ctx();
+    if (!c) return fail(nullptr, NMF_E_NOMEM, "host allocation failed");
+    c->p = *p;
+    c->m = X->m;
+    c->n = X->n;
+    c->r = p->r;
+    c->rp = round_rank(p->r);
+    c->fmt = X->fmt;
+    c->prod_kernel = choose_kernel(p);
+    c->b.m_pad = round_up(c->m, 128);
+    c->b.n_pad = round_up(c->n, 128);
+    c->ldx = round_up(c->n, 64);
+    c->ldxt = round_up(c->m, 64);
+    plan_product(c->pa, c->prod_kernel, c->m, c->b.m_pad, c->n, c->ldx);
+    plan_product(c->pc, c->prod_kernel, c->n, c->b.n_pad, c->m, c->ldxt);
+    c->b.nsplit_a = c->pa.nsplit;
+    c->b.nsplit_c = c->pc.nsplit;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        fail(nullptr, NMF_E_DEVICE, "no usable HIP device: %s", hipGetErrorString(e));
+        free_all(c);
+        delete c;
+        return NMF_E_DEVICE;
+    }
+    st = alloc_buffers(c);
+    if (st == NMF_OK) st = upload_dense(c, X);
+    if (st == NMF_OK) {
+        // A = X H_w^T reads X and the H slots; C^T = X^T W_y reads X^T and the W slots.
+        c->pa.Z = c->X;
+        c->pa.F_base = c->b.Hf;
+        c->pa.slot_stride = c->n * c->rp;
+        c->pa.sel = nmf::SEL_H_W;
+        c->pa.st = c->b.st;
+        c->pc.Z = c->Xt;
+        c->pc.F_base = c->b.Wf;
+        c->pc.slot_stride = c->m * c->rp;
+        c->pc.sel = nmf::SEL_W_Y;
+        c->pc.st = c->b.st;
+    }
+    if (st == NMF_OK && !(c->nx2 > 0.0))
+        st = fail(c, NMF_E_INVAL, "X is zero: the relative error is undefined");
+    if (st == NMF_OK) st = build_graph(c);
+    if (st != NMF_OK) {
+        g_err = c->err;
+        free_all(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return NMF_OK;
+}
+
+nmf_status nmf_start(nmf_ctx *c, const float *W0, const float *H0, int32_t on_device,
+                     void *stream)
+{
+    if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");
+    if (!W0 || !H0) return fail(c, NMF_E_INVAL, "W0 and H0 must not be NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t m = c->m, n = c->n;
+    const int r = c->r;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const float *w0 = W0, *h0 = H0;
+    if (!on_device) {
+        for (int64_t i = 0; i < m * r; ++i)
+            if (!(W0[i] >= 0.0f) || !std::isfinite(W0[i]))
+                return fail(c, NMF_E_INVAL, "W0 has a negative or non-finite entry at %lld", (long long)i);
+        for (int64_t i = 0; i < (int64_t)r * n; ++i)
+            if (!(H0[i] >= 0.0f) || !std::isfinite(H0[i]))
+                return fail(c, NMF_E_INVAL, "H0 has a negative or non-finite entry at %lld", (long long)i);
+        HIP_TRY(c, hipMemcpyAsync(c->b.stage, W0, sizeof(float) * m * r, hipMemcpyHostToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(c->b.stage + m * r, H0, sizeof(float) * r * n,
+                                  hipMemcpyHostToDevice, s));
+        w0 = c->b.stage;
+        h0 = c->b.stage + m * r;
+    }
+    DevState &h = c->hs;
+    std::memset(&h, 0, sizeof(h));
+    h.hp = c->p.hp;
+    h.w_acc = h.w_y = 0;
+    h.h_acc = h.h_y = 0;
+    nmf::plan_slots(0, 0, &h.w_n, &h.w_yn);
+    nmf::plan_slots(0, 0, &h.h_n, &h.h_yn);
+    h.max_iter = c->p.max_iter;
+    h.flags = c->p.flags;
+    h.r = r;
+    h.beta = c->p.beta0;        // beta of iteration 1
+    h.betabar = 1.0;            // upper bound, once per solve
+    h.beta_prev = c->p.beta0;
+    h.beta_acc = c->p.beta0;
+    h.nx2 = c->nx2;
+    h.tol = c->p.tol;
+    h.gamma = c->p.gamma;
+    h.gamma_bar = c->p.gamma_bar;
+    h.eta = c->p.eta;
+    const int rp = c->rp;
+    Buffers &b = c->b;
+    HIP_TRY(c, hipMemcpyAsync(b.st, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * nmf::CNT_N, s));
+    HIP_TRY(c, nmf::launch_pack(rp, m, n, r, w0, h0, b, s));
+    HIP_TRY(c, nmf::launch_setup_gram_h(rp, n, r, b, s));
+    nmf::ProdArgs a0 = c->pa;
+    a0.sel = nmf::SEL_SLOT0;   // A = X H0^T for e(0)
+    HIP_TRY(c, nmf::launch_product(rp, c->p.x_dtype, c->prod_kernel, a0, s));
+    HIP_TRY(c, nmf::launch_setup_error(rp, m, r, b, s));
+    HIP_TRY(c, hipMemcpyAsync(&h, b.st, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->started = false;
+    if (h.bad_input) return fail(c, NMF_E_INVAL, "W0 or H0 has a negative or non-finite entry");
+    if (!std::isfinite(h.e0)) return fail(c, NMF_E_NUMERIC, "the initial error e(0) is not finite");
+    c->started = true;
+    c->launched = 0;
+    return NMF_OK;
+}
+
+nmf_status nmf_iterate(nmf_ctx *c, int32_t iters, void *stream)
+{
+    if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");
+    if (!c->started) return fail(c, NMF_E_STATE, "nmf_iterate before a successful nmf_start");
+    if (iters < 0) return fail(c, NMF_E_INVAL, "iters = %d must be >= 0", iters);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t todo = std::min<int32_t>(iters, c->p.max_iter - c->launched);
+    for (int32_t i = 0; i < todo; ++i) HIP_TRY(c, hipGraphLaunch(c->exec, s));
+    c->launched += std::max(todo, 0);
+    return NMF_OK;
+}
+
+nmf_status nmf_read(nmf_ctx *c, float *W, float *H, int32_t on_device, double *trace,
+                    int32_t trace_cap, int32_t *n_iter, uint8_t *accepted, double *beta,
+                    void *stream)
+{
+    if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");
+    if (!c->started) return fail(c, NMF_E_STATE, "nmf_read before a successful nmf_start");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(c, hipStreamSynchronize(s));
+    DevState &h = c->hs;
+    HIP_TRY(c, hipMemcpy(&h, c->b.st, sizeof(h), hipMemcpyDeviceToHost));
+    const int32_t k = h.k;
+    if (trace && trace_cap < k + 1)
+        return fail(c, NMF_E_INVAL, "trace_cap = %d < %d", trace_cap, k + 1);
+    const int64_t m = c->m, n = c->n;
+    const int r = c->r;
+    if (W || H) {
+        float *dw = on_device ? W : c->b.stage;
+        float *dh = on_device ? H : c->b.stage + m * r;
+        if (on_device && (!W || !H)) return fail(c, NMF_E_INVAL, "device W and H must both be given");
+        HIP_TRY(c, nmf::launch_unpack(c->rp, m, n, r, c->b, dw, dh, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        if (!on_device) {
+            if (W) HIP_TRY(c, hipMemcpy(W, dw, sizeof(float) * m * r, hipMemcpyDeviceToHost));
+            if (H) HIP_TRY(c, hipMemcpy(H, dh, sizeof(float) * r * n, hipMemcpyDeviceToHost));
+        }
+    }
+    if (trace) HIP_TRY(c, hipMemcpy(trace, c->b.trace, sizeof(double) * (k + 1), hipMemcpyDeviceToHost));
+    if (accepted && k > 0)
+        HIP_TRY(c, hipMemcpy(accepted, c->b.accepted, (size_t)k, hipMemcpyDeviceToHost));
+    if (beta && k > 0)
+        HIP_TRY(c, hipMemcpy(beta, c->b.beta_used, sizeof(double) * k, hipMemcpyDeviceToHost));
+    if (n_iter) *n_iter = k;
+    return NMF_OK;
+}
+
+nmf_status nmf_solve(nmf_ctx *c, const float *W0, const float *H0, float *W, float *H,
+                     double *trace, int32_t trace_cap, int32_t *n_iter, uint8_t *accepted,
+                     double *beta)
+{
+    if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");
+    if (!W || !H || !trace || !n_iter) return fail(c, NMF_E_INVAL, "W, H, trace and n_iter are required");
+    if (trace_cap < c->p.max_iter + 1)
+        return fail(c, NMF_E_INVAL, "trace_cap = %d < max_iter + 1 = %d", trace_cap, c->p.max_iter + 1);
+    nmf_status st = nmf_start(c, W0, H0, 0, c->own);
+    if (st != NMF_OK) return st;
+    st = nmf_iterate(c, c->p.max_iter, c->own);
+    if (st != NMF_OK) return st;
+    return nmf_read(c, W, H, 0, trace, trace_cap, n_iter, accepted, beta, c->own);
+}
+
+nmf_status nmf_profile(nmf_ctx *c, int32_t iters, void *stream, double *ms)
+{
+    if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");
+    if (!c->started) return fail(c, NMF_E_STATE, "nmf_profile before a successful nmf_start");
+    if (iters < 1 || !ms) return fail(c, NMF_E_INVAL, "need iters >= 1 and ms != NULL");
+    if (c->launched + iters > c->p.max_iter)
+        return fail(c, NMF_E_INVAL, "only %d iterations left before max_iter",
+                    c->p.max_iter - c->launched);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(c, hipSetDevice(c->device));
+    std::vector<hipEvent_t> ev((size_t)iters * 5, nullptr);
+    nmf_status st = NMF_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            st = fail(c, NMF_E_DEVICE, "hipEventCreate failed");
+            break;
+        }
+    for (int32_t i = 0; st == NMF_OK && i < iters; ++i) st = enqueue_iteration(c, s, &ev[(size_t)i * 5]);
+    if (st == NMF_OK) {
+        c->launched += iters;
+        double acc[4] = {0, 0, 0, 0};
+        hipError_t e = hipEventSynchronize(ev.back());
+        for (int32_t i = 0; e == hipSuccess && i < iters; ++i)
+            for (int ph = 0; ph < 4 && e == hipSuccess; ++ph) {
+                float t = 0.f;
+                e = hipEventElapsedTime(&t, ev[(size_t)i * 5 + ph], ev[(size_t)i * 5 + ph + 1]);
+                acc[ph] += t;
+            }
+        if (e != hipSuccess) st = fail(c, NMF_E_DEVICE, "event timing failed: %s", hipGetErrorString(e));
+        for (int ph = 0; ph < 4; ++ph) ms[ph] = acc[ph] / iters;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
+}
+
+void nmf_destroy(nmf_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    free_all(c);
+    delete c;
+}
+
+const char *nmf_last_error(const nmf_ctx *c)
+{
+    if (c) return c->err.c_str();
+    return g_err.c_str();
+}
+
+}  // extern "C"

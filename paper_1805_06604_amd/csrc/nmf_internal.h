@@ -1,0 +1,141 @@
+// Internal declarations shared by the kernels and the host engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace nmf {
+
+// Three buffers per factor: the accepted iterate, the NNLS output and the
+// extrapolated point. Which buffer plays which role lives in DevState, so an
+// accept or a restart (Algorithm 2) is an index flip taken on the device.
+constexpr int kSlots = 3;
+
+// Rows handled by one workgroup of the sweep and Gram kernels.
+constexpr int kRowsPerBlock = 256;
+
+// Slot selectors for the product kernels.
+enum FactorSel : int32_t {
+    SEL_W_Y = 0,     // W_y: warm start of the coming W update, input of X^T W_y
+    SEL_H_W = 1,     // H used by the W update: H_n (hp = 1) or H_y (hp >= 2)
+    SEL_SLOT0 = 2,   // slot 0, unconditionally (set-up of e(0))
+};
+
+// Solver state kept in device memory and updated only by the decision step.
+struct DevState {
+    int32_t k;              // completed outer iterations
+    int32_t done;           // 1: iterations are no-ops (max_iter or tol reached)
+    int32_t bad_input;      // set by the packing kernels
+    int32_t hp;
+    int32_t w_acc, w_y, w_n, w_yn;   // W slots: accepted, warm start, new, new extrapolated
+    int32_t h_acc, h_y, h_n, h_yn;   // H slots, same roles
+    int32_t max_iter, flags, r, pad0;
+    double beta, betabar, beta_prev, beta_acc;
+    double e_prev, e_acc, nx2, tol;
+    double gamma, gamma_bar, eta, e0;
+};
+
+// Gram buffers (FP64) hold RP*RP entries followed by RP inverse diagonal
+// entries (0 where the coordinate is skipped: beyond r, or a zero diagonal).
+__host__ __device__ constexpr int gram_stride(int rp) { return rp * rp + rp; }
+
+// Slots written by the coming iteration, given the accepted and warm-start
+// slots: the NNLS output goes to a slot that is neither, and the new
+// extrapolated point overwrites the warm start (each row is read before it is
+// written, by the same thread) unless the warm start is the accepted iterate.
+__host__ __device__ inline void plan_slots(int acc, int y, int32_t *n, int32_t *yn)
+{
+    if (acc == y) {
+        *n = (acc + 1) % kSlots;
+        *yn = (acc + 2) % kSlots;
+    } else {
+        *n = kSlots - acc - y;
+        *yn = y;
+    }
+}
+
+// One X-streaming product Y = Z F (see the product kernels). Z is X or the
+// resident X^T with rows padded to a multiple of 128 and rows of length ld (a
+// multiple of 64), zero-filled; Y holds nsplit partial sums over K-chunks.
+struct ProdArgs {
+    const void *Z;          // rows_pad x ld, storage dtype
+    int64_t ld;             // row length of Z
+    int64_t K;              // contraction length (rows of F)
+    int64_t rows;           // true rows of Z
+    int64_t rows_pad;       // multiple of 128
+    const float *F_base;    // factor slots, K x RP each
+    int64_t slot_stride;
+    int sel;                // FactorSel
+    const DevState *st;
+    double *Y;              // nsplit x rows_pad x RP partial sums (FP64)
+    int64_t kchunk;         // K per split, multiple of 64
+    int nsplit;
+};
+
+// Product kernels: VALU FP64 FMA over FP32 operands (products exact, sums in
+// FP64), or matrix cores with operands split into BF16 parts keeping the part
+// pairs of relative weight >= 2^-8 (L = 1) or >= 2^-16 (L = 2), summed in
+// FP32 within a K-chunk.
+enum ProdKernel { PK_VALU = 0, PK_MFMA_L1 = 1, PK_MFMA_L2 = 2 };
+
+// Device buffers of one context. Factors are FP32, row-major with RP columns
+// (r rounded up to a multiple of 16; the padding stays zero):
+//   W slots: m x RP each, H slots hold H^T: n x RP each.
+// Everything that enters the HALS numerator c_k - G(k,:) x (linear terms,
+// Grams) is FP64.
+struct Buffers {
+    float *Wf = nullptr;     // kSlots * m * RP
+    float *Hf = nullptr;     // kSlots * n * RP
+    double *GW = nullptr;    // kSlots * gram_stride: Gram of each W slot
+    double *GH = nullptr;    // gram_stride: Gram of H_w
+    double *A = nullptr;     // nsplit_a x m_pad x RP : partials of X H_w^T
+    double *Ct = nullptr;    // nsplit_c x n_pad x RP : partials of X^T W_y
+    int nsplit_a = 1, nsplit_c = 1;
+    int64_t m_pad = 0, n_pad = 0;
+    double *part_g = nullptr;// per-block partial Grams: nblk * 2 * RP * RP
+    double *part_d = nullptr;// per-block FP64 partials: nblk * 2
+    uint32_t *counters = nullptr; // last-block counters (zeroed; reset by the kernels)
+    DevState *st = nullptr;
+    double *trace = nullptr; // max_iter + 1
+    uint8_t *accepted = nullptr;
+    double *beta_used = nullptr;
+    float *stage = nullptr;  // staging of W0 / H0 / outputs: (m + n) * r
+};
+
+enum Counter { CNT_H = 0, CNT_W = 1, CNT_G = 2, CNT_N = 4 };
+
+// ------------------------------------------------------------ launchers
+// All return hipGetLastError() after enqueueing on `s`.
+hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hipStream_t s);
+
+hipError_t launch_sweep_h(int rp, int64_t n, int r, int inner_k, const Buffers &b,
+                          int64_t m, hipStream_t s);
+hipError_t launch_sweep_w(int rp, int64_t m, int r, int inner_k, const Buffers &b,
+                          int64_t n, hipStream_t s);
+
+// Set-up of e(0): Gram of H0 (slot 0) into GH, then Gram of W0 (slot 0) into
+// GW[0] together with <W0, A>, and the initial error into the state.
+hipError_t launch_setup_gram_h(int rp, int64_t n, int r, const Buffers &b, hipStream_t s);
+hipError_t launch_setup_error(int rp, int64_t m, int r, const Buffers &b, hipStream_t s);
+
+// Packing: W0 (m x r) -> W slot 0 (m x RP); H0 (r x n) -> H slot 0 (n x RP),
+// flagging negative or non-finite entries in st->bad_input.
+hipError_t launch_pack(int rp, int64_t m, int64_t n, int r, const float *W0,
+                       const float *H0, const Buffers &b, hipStream_t s);
+// Unpacking of the accepted slots into W (m x r) and H (r x n).
+hipError_t launch_unpack(int rp, int64_t m, int64_t n, int r, const Buffers &b,
+                         float *W, float *H, hipStream_t s);
+
+// X conversion at create: source FP32 (m x n) -> X (rows of length ldx) and
+// X^T (rows of length ldxt) in the storage type; padding must be zero already.
+hipError_t launch_convert_x(const float *src, int64_t m, int64_t n, int xdtype,
+                            void *X, int64_t ldx, void *Xt, int64_t ldxt, hipStream_t s);
+// ||X||^2 in FP64 (deterministic two-pass reduction) of FP32 values, or of
+// values stored as xdtype.
+hipError_t launch_sumsq(const float *src, int64_t count, double *part, int nblk,
+                        double *out, hipStream_t s);
+hipError_t launch_sumsq_typed(const void *v, int xdtype, int64_t count, double *part,
+                              int nblk, double *out, hipStream_t s);
+
+}  // namespace nmf

@@ -1,0 +1,78 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/nmf.h declares, and validates arguments before any device work."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1805_06604_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "nmf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nmf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    names = declared_functions()
+    assert names, "no declarations found"
+    assert sorted(P.EXPORTS) == names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_defaults_are_the_papers_final_parameters():
+    prm = P.make_params(20)
+    assert (prm.hp, prm.beta0, prm.eta, prm.gamma, prm.gamma_bar) == (3, 0.5, 1.5, 1.01, 1.005)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(hp=0), P.Status.E_INVAL),
+    (dict(hp=4), P.Status.E_INVAL),
+    (dict(beta0=-0.1), P.Status.E_INVAL),
+    (dict(beta0=1.0), P.Status.E_INVAL),
+    (dict(gamma=1.004), P.Status.E_INVAL),          # gamma <= gamma_bar
+    (dict(eta=1.0), P.Status.E_INVAL),              # eta <= gamma
+    (dict(gamma_bar=1.0), P.Status.E_INVAL),
+    (dict(inner_k=0), P.Status.E_INVAL),
+    (dict(max_iter=-1), P.Status.E_INVAL),
+    (dict(tol=-1.0), P.Status.E_INVAL),
+    (dict(x_dtype=7), P.Status.E_INVAL),
+    (dict(prod=9), P.Status.E_INVAL),
+    (dict(flags=8), P.Status.E_INVAL),
+    (dict(inner_rule=3), P.Status.E_UNSUPPORTED),
+])
+def test_parameter_validation(kw, status):
+    with pytest.raises(P.NMFError) as e:
+        P.Solver(np.ones((4, 3), np.float32), 2, **kw)
+    assert e.value.status == status
+
+
+@pytest.mark.parametrize("r,status", [(0, P.Status.E_INVAL), (65, P.Status.E_UNSUPPORTED)])
+def test_rank_validation(r, status):
+    with pytest.raises(P.NMFError) as e:
+        P.Solver(np.ones((4, 3), np.float32), r)
+    assert e.value.status == status
+
+
+def test_nonfinite_matrix_rejected():
+    X = np.ones((5, 4), np.float32)
+    X[2, 1] = np.nan
+    with pytest.raises(P.NMFError) as e:
+        P.Solver(X, 2)
+    assert e.value.status == P.Status.E_INVAL
+    assert "non-finite" in str(e.value)
+
+
+def test_empty_matrix_rejected():
+    with pytest.raises(P.NMFError) as e:
+        P.Solver(np.ones((0, 3), np.float32), 1)
+    assert e.value.status == P.Status.E_INVAL

@@ -141,15 +141,17 @@ def test_sweeps_converge_to_brute_force_nnls_w(seed):
 
 
 def test_zero_denominator_keeps_the_coordinate():
-    """A zero column of W makes ||W(:,k)||^2 = 0; that row of H is left as
-    it is (any value minimizes, since it multiplies a zero column)."""
+    """A zero column of W makes ||W(:,k)||^2 = 0; that row of H does not
+    enter the objective, so any nonnegative value minimizes: it is kept where
+    nonnegative and projected to 0 where the warm start was negative."""
     rng = np.random.default_rng(3)
     W = rng.random((6, 3))
     W[:, 1] = 0.0
     X = rng.random((6, 4))
     H0 = rng.random((3, 4))
+    H0[1, 2] = -0.5
     H = oracle.nnls_h(X, W, H0, sweeps=50)
-    np.testing.assert_array_equal(H[1], H0[1])
+    np.testing.assert_array_equal(H[1], np.maximum(H0[1], 0.0))
     Wk = W[:, [0, 2]]
     for c in range(4):
         np.testing.assert_allclose(H[[0, 2], c], brute_force_nnls(Wk, X[:, c]),
