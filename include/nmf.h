@@ -57,12 +57,14 @@ typedef enum { NMF_INNER_FIXED = 0 } nmf_inner;
  *   AUTO       : MFMA_EXACT for FP32 X, MFMA_FAST for BF16 and FP16 X.
  *   VALU       : FP64 FMA on the vector ALUs (exact products of the stored
  *                values, FP64 sums): the reference-accuracy path, slowest.
- *   MFMA_EXACT : matrix cores. Each FP32 operand is split exactly into three
- *                BF16 parts of 8 significant bits and every part product of
- *                relative weight >= 2^-16 is accumulated in FP32 within a
- *                K-chunk: products as accurate as FP32 arithmetic.
- *   MFMA_FAST  : matrix cores with operands carried to 16 significant bits
- *                (part products of weight >= 2^-8). */
+ *   MFMA_EXACT : integer matrix cores. X is stored as four int8 slices per
+ *                entry with a power-of-two scale per row (4 bytes per entry,
+ *                whatever x_dtype; the x_dtype-rounded values are sliced), the
+ *                factor is sliced per column the same way, and the slice
+ *                products are summed exactly in int32: products to about
+ *                2^-27 of the row and column maxima, no rounding over K.
+ *   MFMA_FAST  : BF16 matrix cores, operands carried to 16 significant bits,
+ *                sums in FP32 within a K-chunk. X keeps its x_dtype storage. */
 typedef enum {
     NMF_PROD_AUTO = 0,
     NMF_PROD_VALU = 1,

@@ -24,6 +24,8 @@ struct nmf_ctx {
     void *X = nullptr;   // m_pad x ldx, storage dtype, zero padding
     void *Xt = nullptr;  // n_pad x ldxt
     int64_t ldx = 0, ldxt = 0;
+    int *zexp_x = nullptr;   // exact-integer path: row scale exponents of X
+    int *zexp_xt = nullptr;  // and of X^T
     int prod_kernel = nmf::PK_MFMA_L2;
     nmf::ProdArgs pa{};  // A = X H_w^T
     nmf::ProdArgs pc{};  // C^T = X^T W_y
@@ -71,9 +73,9 @@ int choose_kernel(const nmf_params *p)
 {
     switch (p->prod) {
     case NMF_PROD_VALU: return nmf::PK_VALU;
-    case NMF_PROD_MFMA_EXACT: return nmf::PK_MFMA_L2;
+    case NMF_PROD_MFMA_EXACT: return nmf::PK_MFMA_I8;
     case NMF_PROD_MFMA_FAST: return nmf::PK_MFMA_L1;
-    default: return p->x_dtype == NMF_X_F32 ? nmf::PK_MFMA_L2 : nmf::PK_MFMA_L1;
+    default: return p->x_dtype == NMF_X_F32 ? nmf::PK_MFMA_I8 : nmf::PK_MFMA_L1;
     }
 }
 
@@ -93,7 +95,9 @@ void plan_product(nmf::ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, 
     }
     const int64_t rb = rows_pad / 128, tiles = ld / 64;
     int64_t want = (512 + rb - 1) / rb;
-    want = std::max<int64_t>(1, std::min<int64_t>({want, tiles, 32}));
+    // The exact-integer sums stay below 2^31 for chunks of at most 65536.
+    if (kernel == nmf::PK_MFMA_I8) want = std::max<int64_t>(want, (tiles + 1023) / 1024);
+    want = std::max<int64_t>(1, std::min<int64_t>({want, tiles, 64}));
     a.kchunk = ((tiles + want - 1) / want) * 64;
     a.nsplit = (int)((ld + a.kchunk - 1) / a.kchunk);
 }
@@ -153,8 +157,8 @@ void free_all(nmf_ctx *c)
 {
     if (c->exec) (void)hipGraphExecDestroy(c->exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
-    void *ptrs[] = {c->X, c->Xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH, c->b.A, c->b.Ct,
-                    c->b.part_g, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
+    void *ptrs[] = {c->X, c->Xt, c->zexp_x, c->zexp_xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH,
+                    c->b.A, c->b.Ct, c->b.part_g, c->b.part_m, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
                     c->b.accepted, c->b.beta_used, c->b.stage};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -183,6 +187,7 @@ nmf_status alloc_buffers(nmf_ctx *c)
     c->pa.Y = b.A;
     c->pc.Y = b.Ct;
     HIP_TRY(c, dalloc(&b.part_g, (size_t)nblk * 2 * rp * rp));
+    HIP_TRY(c, dalloc(&b.part_m, (size_t)nblk * 2 * rp));
     HIP_TRY(c, dalloc(&b.part_d, (size_t)std::max<int64_t>(nblk * 2, 1024)));
     HIP_TRY(c, dalloc(&b.counters, (size_t)nmf::CNT_N));
     HIP_TRY(c, hipMemset(b.counters, 0, sizeof(uint32_t) * nmf::CNT_N));
@@ -223,6 +228,26 @@ nmf_status upload_dense(nmf_ctx *c, const nmf_matrix *X)
     if (nx2) (void)hipFree(nx2);
     if (e != hipSuccess)
         return fail(c, NMF_E_DEVICE, "uploading X failed: %s", hipGetErrorString(e));
+    if (c->prod_kernel == nmf::PK_MFMA_I8) {
+        // Keep only the int8 slices of X and X^T (4 bytes per entry).
+        void *xs = nullptr, *xts = nullptr;
+        HIP_TRY(c, hipMalloc(&xs, (size_t)c->b.m_pad * c->ldx * 4));
+        HIP_TRY(c, hipMalloc(&xts, (size_t)c->b.n_pad * c->ldxt * 4));
+        HIP_TRY(c, hipMemset(xs, 0, (size_t)c->b.m_pad * c->ldx * 4));
+        HIP_TRY(c, hipMemset(xts, 0, (size_t)c->b.n_pad * c->ldxt * 4));
+        HIP_TRY(c, dalloc(&c->zexp_x, (size_t)c->b.m_pad));
+        HIP_TRY(c, dalloc(&c->zexp_xt, (size_t)c->b.n_pad));
+        HIP_TRY(c, hipMemset(c->zexp_x, 0, sizeof(int) * c->b.m_pad));
+        HIP_TRY(c, hipMemset(c->zexp_xt, 0, sizeof(int) * c->b.n_pad));
+        HIP_TRY(c, nmf::i8::slice_rows(c->X, xd, c->m, c->n, c->ldx, c->ldx, xs, c->zexp_x, c->own));
+        HIP_TRY(c, nmf::i8::slice_rows(c->Xt, xd, c->n, c->m, c->ldxt, c->ldxt, xts, c->zexp_xt,
+                                       c->own));
+        HIP_TRY(c, hipStreamSynchronize(c->own));
+        (void)hipFree(c->X);
+        (void)hipFree(c->Xt);
+        c->X = xs;
+        c->Xt = xts;
+    }
     return NMF_OK;
 }
 
@@ -328,11 +353,17 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
         c->pa.slot_stride = c->n * c->rp;
         c->pa.sel = nmf::SEL_H_W;
         c->pa.st = c->b.st;
+        c->pa.zexp = c->zexp_x;
+        c->pa.gram_base = c->b.GH;
+        c->pa.gram_slot_stride = 0;
         c->pc.Z = c->Xt;
         c->pc.F_base = c->b.Wf;
         c->pc.slot_stride = c->m * c->rp;
         c->pc.sel = nmf::SEL_W_Y;
         c->pc.st = c->b.st;
+        c->pc.zexp = c->zexp_xt;
+        c->pc.gram_base = c->b.GW;
+        c->pc.gram_slot_stride = nmf::gram_stride(c->rp);
     }
     if (st == NMF_OK && !(c->nx2 > 0.0))
         st = fail(c, NMF_E_INVAL, "X is zero: the relative error is undefined");

@@ -179,6 +179,9 @@ __global__ void sum_parts_kernel(const double *__restrict__ part, int nblk, doub
 
 }  // namespace
 
+namespace i8 {
+void launch(int rp, const ProdArgs &a, hipStream_t s);
+}
 namespace mfma {
 void launch_f32(int rp, int L, const ProdArgs &a, hipStream_t s);
 void launch_bf16(int rp, int L, const ProdArgs &a, hipStream_t s);
@@ -195,6 +198,10 @@ hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hip
         case 2: return prod_fp64_dispatch<__half>(rp, a, s);
         default: return hipErrorInvalidValue;
         }
+    }
+    if (kernel == PK_MFMA_I8) {
+        i8::launch(rp, a, s);
+        return hipGetLastError();
     }
     const int L = (kernel == PK_MFMA_L2) ? 2 : 1;
     switch (xdtype) {

@@ -37,7 +37,7 @@ __global__ void pack_kernel(int rp, int64_t m, int64_t n, int r,
         }
         if (!(v >= 0.0f) || !isfinite(v)) bad = true;
     }
-    if (bad) atomicOr(&st->bad_input, 1);
+    if (bad) __hip_atomic_fetch_or(&st->bad_input, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ void unpack_kernel(int rp, int64_t m, int64_t n, int r,

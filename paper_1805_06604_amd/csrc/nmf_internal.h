@@ -36,9 +36,11 @@ struct DevState {
     double gamma, gamma_bar, eta, e0;
 };
 
-// Gram buffers (FP64) hold RP*RP entries followed by RP inverse diagonal
-// entries (0 where the coordinate is skipped: beyond r, or a zero diagonal).
-__host__ __device__ constexpr int gram_stride(int rp) { return rp * rp + rp; }
+// Gram buffers (FP64) hold RP*RP entries, then RP inverse diagonal entries
+// (0 where the coordinate is skipped: beyond r, or a zero diagonal), then the
+// RP column maxima max |F(:,k)| of the factor (scales of the exact-integer
+// products).
+__host__ __device__ constexpr int gram_stride(int rp) { return rp * rp + 2 * rp; }
 
 // Slots written by the coming iteration, given the accepted and warm-start
 // slots: the NNLS output goes to a slot that is neither, and the new
@@ -71,13 +73,18 @@ struct ProdArgs {
     double *Y;              // nsplit x rows_pad x RP partial sums (FP64)
     int64_t kchunk;         // K per split, multiple of 64
     int nsplit;
+    // Exact-integer kernel only: per-row scale exponents of Z, and the Gram
+    // buffers whose tail holds the column maxima of each factor slot.
+    const int *zexp;
+    const double *gram_base;
+    int64_t gram_slot_stride;
 };
 
 // Product kernels: VALU FP64 FMA over FP32 operands (products exact, sums in
 // FP64), or matrix cores with operands split into BF16 parts keeping the part
 // pairs of relative weight >= 2^-8 (L = 1) or >= 2^-16 (L = 2), summed in
 // FP32 within a K-chunk.
-enum ProdKernel { PK_VALU = 0, PK_MFMA_L1 = 1, PK_MFMA_L2 = 2 };
+enum ProdKernel { PK_VALU = 0, PK_MFMA_L1 = 1, PK_MFMA_L2 = 2, PK_MFMA_I8 = 3 };
 
 // Device buffers of one context. Factors are FP32, row-major with RP columns
 // (r rounded up to a multiple of 16; the padding stays zero):
@@ -94,6 +101,7 @@ struct Buffers {
     int nsplit_a = 1, nsplit_c = 1;
     int64_t m_pad = 0, n_pad = 0;
     double *part_g = nullptr;// per-block partial Grams: nblk * 2 * RP * RP
+    double *part_m = nullptr;// per-block column maxima: nblk * 2 * RP
     double *part_d = nullptr;// per-block FP64 partials: nblk * 2
     uint32_t *counters = nullptr; // last-block counters (zeroed; reset by the kernels)
     DevState *st = nullptr;
@@ -103,7 +111,8 @@ struct Buffers {
     float *stage = nullptr;  // staging of W0 / H0 / outputs: (m + n) * r
 };
 
-enum Counter { CNT_H = 0, CNT_W = 1, CNT_G = 2, CNT_N = 4 };
+// Last-block counters, one per kernel kind, each on its own 256-byte line.
+enum Counter { CNT_H = 0, CNT_W = 64, CNT_G = 128, CNT_N = 192 };
 
 // ------------------------------------------------------------ launchers
 // All return hipGetLastError() after enqueueing on `s`.
@@ -126,6 +135,13 @@ hipError_t launch_pack(int rp, int64_t m, int64_t n, int r, const float *W0,
 // Unpacking of the accepted slots into W (m x r) and H (r x n).
 hipError_t launch_unpack(int rp, int64_t m, int64_t n, int r, const Buffers &b,
                          float *W, float *H, hipStream_t s);
+
+// Exact-integer path: slices the rows of a typed row-major matrix (rows x cols,
+// rows of length ld_src) into int8 slices with rows of ld_dst entries.
+namespace i8 {
+hipError_t slice_rows(const void *src, int xdtype, int64_t rows, int64_t cols, int64_t ld_src,
+                      int64_t ld_dst, void *dst, int *zexp, hipStream_t s);
+}
 
 // X conversion at create: source FP32 (m x n) -> X (rows of length ldx) and
 // X^T (rows of length ldxt) in the storage type; padding must be zero already.

@@ -173,17 +173,19 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 }
 
 // Partial Gram v v^T of the block's 256 rows (FP32 values, FP64 products and
-// sums), written to out (RP*RP). Each wave's 64 rows pass through an LDS tile
-// in turn.
+// sums), written to out (RP*RP), and the block's column maxima max |v_k|,
+// written to out_max (RP). Each wave's 64 rows pass through an LDS tile in
+// turn.
 template <int RP>
 __device__ void block_gram(const float (&v)[RP], double *__restrict__ out,
-                           float (*tile)[RP + 1])
+                           double *__restrict__ out_max, float (*tile)[RP + 1])
 {
     constexpr int PER = RP * RP / kThreads;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     double acc[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) acc[q] = 0.0;
+    float cmax = 0.0f;
     for (int w = 0; w < kThreads / 64; ++w) {
         if (wave == w) {
 #pragma unroll
@@ -198,20 +200,27 @@ __device__ void block_gram(const float (&v)[RP], double *__restrict__ out,
                 a = fma((double)tile[row][k], (double)tile[row][l], a);
             acc[q] = a;
         }
+        if (tid < RP)
+            for (int row = 0; row < 64; ++row) cmax = fmaxf(cmax, fabsf(tile[row][tid]));
         __syncthreads();
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) out[tid + kThreads * q] = acc[q];
+    if (tid < RP) out_max[tid] = cmax;
 }
 
 // Marks this block done; returns true in every thread of the last block to
-// finish. Partials written before the call are visible to that block.
+// finish. Partials written before the call are visible to that block. The
+// blocks of a grid run on all XCDs, whose L2 caches are not coherent with one
+// another, so the counter is updated at system scope (coherent at memory);
+// the fences write back and invalidate the L2 for the partials.
 __device__ inline bool last_block(uint32_t *counter, int *s_flag)
 {
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t prev = atomicAdd(counter, 1u);
+        const uint32_t prev =
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
         *s_flag = (prev == gridDim.x - 1);
     }
     __syncthreads();
@@ -220,13 +229,26 @@ __device__ inline bool last_block(uint32_t *counter, int *s_flag)
     return last;
 }
 
-// Sum of the partial Grams `which` (0 or 1) over nblk blocks in FP64, fixed
-// block order; writes the Gram and its inverse diagonal to G and keeps this
-// thread's entries in g64.
-template <int RP>
-__device__ void finish_gram(const double *__restrict__ part, int nblk, int which,
-                            double *__restrict__ G, int r, double (&g64)[RP * RP / kThreads])
+// Re-arms a last-block counter for the next launch (system scope, like the
+// increments).
+__device__ inline void reset_counter(uint32_t *counter)
 {
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Sum of the partial Grams `which` (0 or 1) over nblk blocks in FP64, fixed
+// block order; writes the Gram, its inverse diagonal and the column maxima
+// to G and keeps this thread's Gram entries in g64.
+template <int RP>
+__device__ void finish_gram(const double *__restrict__ part, const double *__restrict__ part_m,
+                            int nblk, int which, double *__restrict__ G, int r,
+                            double (&g64)[RP * RP / kThreads])
+{
+    if (threadIdx.x < RP) {
+        double mx = 0.0;
+        for (int b = 0; b < nblk; ++b) mx = fmax(mx, part_m[((size_t)b * 2 + which) * RP + threadIdx.x]);
+        G[RP * RP + RP + threadIdx.x] = mx;
+    }
     constexpr int PER = RP * RP / kThreads;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -296,6 +318,7 @@ struct SweepArgs {
     double *GWout;         // = GW (written by the W side)
     double *GH;            // Gram of H_w
     double *part_g;
+    double *part_m;
     double *part_d;
     uint32_t *counter;
     DevState *st;
@@ -355,11 +378,12 @@ __global__ __launch_bounds__(kThreads) void sweep_h_kernel(SweepArgs a)
 #pragma unroll
         for (int k = 0; k < RP; ++k) w[k] = 0.f;
     }
-    block_gram<RP>(w, a.part_g + (size_t)blockIdx.x * 2 * RP * RP, tile);
+    block_gram<RP>(w, a.part_g + (size_t)blockIdx.x * 2 * RP * RP,
+                   a.part_m + (size_t)blockIdx.x * 2 * RP, tile);
     if (!last_block(a.counter, &s_last)) return;
     double g64[RP * RP / kThreads];
-    finish_gram<RP>(a.part_g, a.nblk, 0, a.GH, a.r, g64);
-    if (threadIdx.x == 0) *a.counter = 0;
+    finish_gram<RP>(a.part_g, a.part_m, a.nblk, 0, a.GH, a.r, g64);
+    if (threadIdx.x == 0) reset_counter(a.counter);
 }
 
 // a6 + a7 + a8: W_n from W_y by K sweeps with X H_w^T and H_w H_w^T;
@@ -403,15 +427,16 @@ __global__ __launch_bounds__(kThreads) void sweep_w_kernel(SweepArgs a)
         for (int k = 0; k < RP; ++k) { xf[k] = 0.f; y[k] = 0.f; }
     }
     double *pb = a.part_g + (size_t)blockIdx.x * 2 * RP * RP;
-    block_gram<RP>(xf, pb, tile);
-    block_gram<RP>(y, pb + RP * RP, tile);
+    double *pm = a.part_m + (size_t)blockIdx.x * 2 * RP;
+    block_gram<RP>(xf, pb, pm, tile);
+    block_gram<RP>(y, pb + RP * RP, pm + RP, tile);
     s1 = block_sum(s1, shd);
     if (threadIdx.x == 0) a.part_d[blockIdx.x] = s1;
     if (!last_block(a.counter, &s_last)) return;
 
     double gn[RP * RP / kThreads], gy[RP * RP / kThreads];
-    finish_gram<RP>(a.part_g, a.nblk, 0, a.GWout + (size_t)w_n * gram_stride(RP), a.r, gn);
-    finish_gram<RP>(a.part_g, a.nblk, 1, a.GWout + (size_t)w_yn * gram_stride(RP), a.r, gy);
+    finish_gram<RP>(a.part_g, a.part_m, a.nblk, 0, a.GWout + (size_t)w_n * gram_stride(RP), a.r, gn);
+    finish_gram<RP>(a.part_g, a.part_m, a.nblk, 1, a.GWout + (size_t)w_yn * gram_stride(RP), a.r, gy);
     double s2 = 0.0;
 #pragma unroll
     for (int q = 0; q < RP * RP / kThreads; ++q)
@@ -421,7 +446,7 @@ __global__ __launch_bounds__(kThreads) void sweep_w_kernel(SweepArgs a)
         double t = 0.0;
         for (int b = 0; b < a.nblk; ++b) t += a.part_d[b];
         decide(st, t, s2, a.trace, a.accepted, a.beta_used);
-        *a.counter = 0;
+        reset_counter(a.counter);
     }
 }
 
@@ -444,14 +469,15 @@ __global__ __launch_bounds__(kThreads) void setup_gram_kernel(SweepArgs a, int w
 #pragma unroll
         for (int k = 0; k < RP; ++k) x[k] = 0.f;
     }
-    block_gram<RP>(x, a.part_g + (size_t)blockIdx.x * 2 * RP * RP, tile);
+    block_gram<RP>(x, a.part_g + (size_t)blockIdx.x * 2 * RP * RP,
+                   a.part_m + (size_t)blockIdx.x * 2 * RP, tile);
     if (with_error) {
         s1 = block_sum(s1, shd);
         if (threadIdx.x == 0) a.part_d[blockIdx.x] = s1;
     }
     if (!last_block(a.counter, &s_last)) return;
     double g[RP * RP / kThreads];
-    finish_gram<RP>(a.part_g, a.nblk, 0, a.GWout, a.r, g);
+    finish_gram<RP>(a.part_g, a.part_m, a.nblk, 0, a.GWout, a.r, g);
     if (with_error) {
         double s2 = 0.0;
 #pragma unroll
@@ -471,7 +497,7 @@ __global__ __launch_bounds__(kThreads) void setup_gram_kernel(SweepArgs a, int w
             if (!isfinite(e) || st->max_iter == 0) st->done = 1;
         }
     }
-    if (threadIdx.x == 0) *a.counter = 0;
+    if (threadIdx.x == 0) reset_counter(a.counter);
 }
 
 template <int RP>
@@ -483,6 +509,7 @@ SweepArgs base_args(const Buffers &b, int64_t rows, int r, int K)
     a.K = K;
     a.nblk = (int)((rows + kThreads - 1) / kThreads);
     a.part_g = b.part_g;
+    a.part_m = b.part_m;
     a.part_d = b.part_d;
     a.st = b.st;
     a.trace = b.trace;
