@@ -158,7 +158,7 @@ void free_all(nmf_ctx *c)
     if (c->exec) (void)hipGraphExecDestroy(c->exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     void *ptrs[] = {c->X, c->Xt, c->zexp_x, c->zexp_xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH,
-                    c->b.A, c->b.Ct, c->b.part_g, c->b.part_m, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
+                    c->b.A, c->b.Ct, c->b.part_g, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
                     c->b.accepted, c->b.beta_used, c->b.stage};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -177,6 +177,7 @@ nmf_status alloc_buffers(nmf_ctx *c)
     const int64_t m = c->m, n = c->n;
     const int gs = nmf::gram_stride(rp);
     const int64_t nblk = (std::max(m, n) + nmf::kRowsPerBlock - 1) / nmf::kRowsPerBlock;
+    const int64_t rec = nmf::sweep_record(rp);
     Buffers &b = c->b;
     HIP_TRY(c, dalloc(&b.Wf, (size_t)nmf::kSlots * m * rp));
     HIP_TRY(c, dalloc(&b.Hf, (size_t)nmf::kSlots * n * rp));
@@ -186,9 +187,8 @@ nmf_status alloc_buffers(nmf_ctx *c)
     HIP_TRY(c, dalloc(&b.Ct, (size_t)c->pc.nsplit * b.n_pad * rp));
     c->pa.Y = b.A;
     c->pc.Y = b.Ct;
-    HIP_TRY(c, dalloc(&b.part_g, (size_t)nblk * 2 * rp * rp));
-    HIP_TRY(c, dalloc(&b.part_m, (size_t)nblk * 2 * rp));
-    HIP_TRY(c, dalloc(&b.part_d, (size_t)std::max<int64_t>(nblk * 2, 1024)));
+    HIP_TRY(c, dalloc(&b.part_g, (size_t)(nblk * rec)));
+    HIP_TRY(c, dalloc(&b.part_d, (size_t)1024));
     HIP_TRY(c, dalloc(&b.counters, (size_t)nmf::CNT_N));
     HIP_TRY(c, hipMemset(b.counters, 0, sizeof(uint32_t) * nmf::CNT_N));
     HIP_TRY(c, dalloc(&b.st, 1));

@@ -12,8 +12,12 @@ namespace nmf {
 // accept or a restart (Algorithm 2) is an index flip taken on the device.
 constexpr int kSlots = 3;
 
-// Rows handled by one workgroup of the sweep and Gram kernels.
-constexpr int kRowsPerBlock = 256;
+// Factor rows handled by one workgroup of the sweep kernels (16 per wave).
+constexpr int kRowsPerBlock = 64;
+
+// Per-workgroup record of the sweep kernels: up to two partial Gram matrices
+// with their column maxima, and one FP64 partial sum.
+__host__ __device__ constexpr int64_t sweep_record(int rp) { return 2 * (rp * rp + rp) + 1; }
 
 // Slot selectors for the product kernels.
 enum FactorSel : int32_t {
@@ -100,9 +104,8 @@ struct Buffers {
     double *Ct = nullptr;    // nsplit_c x n_pad x RP : partials of X^T W_y
     int nsplit_a = 1, nsplit_c = 1;
     int64_t m_pad = 0, n_pad = 0;
-    double *part_g = nullptr;// per-block partial Grams: nblk * 2 * RP * RP
-    double *part_m = nullptr;// per-block column maxima: nblk * 2 * RP
-    double *part_d = nullptr;// per-block FP64 partials: nblk * 2
+    double *part_g = nullptr;// per-workgroup records of the sweep kernels
+    double *part_d = nullptr;// FP64 scratch: reduction partials, the summed <W, A>
     uint32_t *counters = nullptr; // last-block counters (zeroed; reset by the kernels)
     DevState *st = nullptr;
     double *trace = nullptr; // max_iter + 1

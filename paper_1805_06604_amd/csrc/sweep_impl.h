@@ -1,161 +1,76 @@
-// Templates of the HALS sweeps with fused epilogues, Gram reductions and the FP64 decision
-// step of E-A-HALS (arXiv 1805.06604: section 1 closed form, Algorithm 2,
+// HALS sweeps with fused epilogues, Gram reductions and the FP64 decision step
+// of E-A-HALS (arXiv 1805.06604: section 1 closed form, Algorithm 2,
 // Algorithm 3, Remark 1).
 //
-// Layout: one factor row per lane. W rows and H^T rows (columns of H) have the
-// same shape (RP floats), so both blocks use the same code; the Gram matrix of
-// the other factor is read with wave-uniform addresses (scalar loads).
+// Each half-iteration is two launches:
+//  * hals_kernel: a workgroup is 4 waves over 64 factor rows, each wave owns
+//    16 rows. The K Gauss-Seidel sweeps of the closed form run in FP64 with
+//    the coordinates in blocks of 16: the block's numerators t = c_b - x G_b
+//    come from the FP64 matrix cores (v_mfma_f64_16x16x4f64, the Gram block in
+//    registers in B-operand order), then the 16 coordinates of the block are
+//    updated in order, lane q of each 16-lane row owning coordinate q and
+//    passing its change to the other lanes with one 64-bit row broadcast
+//    (DPP row_newbcast). The epilogue stores the new factor rows and the
+//    extrapolated rows, and writes one record per workgroup: the partial Gram
+//    matrices (FP64 matrix cores again), column maxima and <W_n, A>.
+//  * finish_kernel: sums the records in a fixed order (deterministic), writes
+//    the Gram matrices with their inverse diagonals and column maxima, and in
+//    its last workgroup forms the error of Remark 1 and takes the decision.
+//
+// Register layout of the 16 x 16 tiles (16 rows of a wave, 16 coordinates):
+// lane l = lr + 16 g holds, in its 4 values v, rows 4 v + g of coordinate lr
+// ("D layout", the accumulator layout of the FP64 MFMA), and for the A operand
+// of the sweep product x[row lr][coordinate 4 s + g] for k-step s.
 #pragma once
 
 #include "nmf_internal.h"
 
-#include <algorithm>
 #include <cmath>
+#include <utility>
 
 namespace nmf {
 namespace sweep {
 
-constexpr int kThreads = kRowsPerBlock;
+typedef double double4v __attribute__((ext_vector_type(4)));
 
-// ---------------------------------------------------------------- row I/O
+constexpr int kWaves = 4;
+constexpr int kRows = kRowsPerBlock;       // rows per workgroup (16 per wave)
+constexpr int kThreads = kWaves * 64;
+static_assert(kRows == kWaves * 16, "one 16-row tile per wave");
 
+enum Mode { SETUP_H = 0, SETUP_W = 1, SWEEP_H = 2, SWEEP_W = 3 };
+
+template <int M>
+struct ModeInfo {
+    static constexpr bool sweeps = (M == SWEEP_H || M == SWEEP_W);
+    static constexpr bool lin = (M != SETUP_H);            // reads the linear term
+    static constexpr bool s1 = (M == SETUP_W || M == SWEEP_W);
+    static constexpr int ngram = (M == SWEEP_W) ? 2 : 1;
+};
+
+// Per-workgroup record: ngram x (RP*RP Gram entries, RP column maxima), then
+// <x, c>.
 template <int RP>
-__device__ __forceinline__ void load_row(const float *__restrict__ p, float (&v)[RP])
+__host__ __device__ constexpr int rec_len(int ngram) { return ngram * (RP * RP + RP) + 1; }
+
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I...>)
 {
-    const float4 *q = reinterpret_cast<const float4 *>(p);
-#pragma unroll
-    for (int i = 0; i < RP / 4; ++i) {
-        const float4 t = q[i];
-        v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w;
-    }
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_(f, std::make_integer_sequence<int, N>{});
 }
 
-template <int RP>
-__device__ __forceinline__ void store_row(float *__restrict__ p, const float (&v)[RP])
+// Value of lane Q of this lane's 16-lane row.
+template <int Q>
+__device__ __forceinline__ double row_bcast(double v)
 {
-    float4 *q = reinterpret_cast<float4 *>(p);
-#pragma unroll
-    for (int i = 0; i < RP / 4; ++i)
-        q[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
-}
-
-// Linear term of one row: the product kernel's K-chunk partials are summed in
-// FP64, in a fixed order, into the first partial slice (the row belongs to
-// this thread alone); returns the row's address there.
-template <int RP>
-__device__ __forceinline__ const double *sum_lin(double *__restrict__ lin, int nsplit,
-                                                 int64_t split_stride, int64_t row)
-{
-    double *dst = lin + row * RP;
-    if (nsplit > 1) {
-#pragma unroll
-        for (int q = 0; q < RP / 2; ++q) {
-            double2 acc = *reinterpret_cast<const double2 *>(dst + 2 * q);
-            for (int sp = 1; sp < nsplit; ++sp) {
-                const double2 v = *reinterpret_cast<const double2 *>(dst + sp * split_stride + 2 * q);
-                acc.x += v.x;
-                acc.y += v.y;
-            }
-            *reinterpret_cast<double2 *>(dst + 2 * q) = acc;
-        }
-    }
-    return dst;
-}
-
-// <x, c> in FP64 for an FP32 row x and an FP64 row c in memory.
-template <int RP>
-__device__ __forceinline__ double dot_lin(const float (&x)[RP], const double *__restrict__ c)
-{
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < RP / 2; ++q) {
-        const double2 v = *reinterpret_cast<const double2 *>(c + 2 * q);
-        s = fma((double)x[2 * q], v.x, s);
-        s = fma((double)x[2 * q + 1], v.y, s);
-    }
-    return s;
-}
-
-// --------------------------------------------------------------- the sweep
-
-// K sweeps of the HALS closed form over the coordinates of one row x, with
-// linear term c (a row of X H^T, or a column of W^T X) and the symmetric Gram
-// matrix G of the fixed factor (section 1):
-//     x_k <- max(0, x_k + (c_k - G(k,:) x) / G(k,k)),   k ascending,
-// each update used at once (Gauss-Seidel); this is the Sigma_{j != k} form of
-// the paper written around the current x_k. The numerator is a difference of
-// nearly equal terms once the iterate settles, so x, c, G and the sums are
-// FP64. The coordinates go in blocks of 16: t = c_b - G(b,:) x is formed for
-// the whole block with 16 independent accumulators (one uniform load of a
-// Gram row segment feeds 16 FMAs), then the block is updated in order, each
-// change of x_k corrected into the t of the later coordinates of the block. A
-// zero inverse diagonal (k >= r, or a zero G(k,k)) leaves max(0, x_k).
-typedef const __attribute__((address_space(4))) double *gram_ptr;
-
-// Loads N consecutive Gram entries with wave-uniform (scalar) loads.
-template <int N>
-__device__ __forceinline__ void load_g(double (&g)[N], gram_ptr p)
-{
-#pragma unroll
-    for (int q = 0; q < N; ++q) g[q] = p[q];
-}
-
-// Coordinates per Gauss-Seidel block of the sweep.
-constexpr int kGS = 8;
-
-// The block loop is a runtime loop and x rotates by kGS registers per block,
-// so that the current block always sits in x[0..kGS): register indices stay
-// static and the loop body stays small enough for the scheduler to keep the
-// scalar Gram loads close to their use. x[j] holds coordinate (j + b) mod RP.
-template <int RP>
-__device__ __forceinline__ void hals_sweeps(double (&x)[RP], const double *crow,
-                                            const double *__restrict__ G, int K)
-{
-    // The Gram matrix is read through the constant address space, so that
-    // every access is a scalar (wave-uniform) load; no block of a sweep
-    // kernel writes the Gram matrix it reads.
-    const gram_ptr Gs = (gram_ptr)G;
-    for (int s = 0; s < K; ++s) {
-#pragma unroll 1
-        for (int b = 0; b < RP; b += kGS) {
-            double t[kGS];
-#pragma unroll
-            for (int q = 0; q < kGS; q += 2) {
-                const double2 v = *reinterpret_cast<const double2 *>(crow + b + q);
-                t[q] = v.x;
-                t[q + 1] = v.y;
-            }
-            // t = c_b - G(b, :) x over the rows of G (= its columns).
-#pragma unroll
-            for (int j = 0; j < RP; ++j) {
-                int l = j + b;
-                if (l >= RP) l -= RP;
-                double g[kGS];
-                load_g<kGS>(g, Gs + l * RP + b);
-#pragma unroll
-                for (int q = 0; q < kGS; ++q) t[q] = fma(-g[q], x[j], t[q]);
-            }
-            // In-block Gauss-Seidel: x_k, then the later t of the block.
-#pragma unroll
-            for (int q = 0; q < kGS; ++q) {
-                const int k = b + q;
-                const double xn = fmax(fma(t[q], (double)Gs[RP * RP + k], x[q]), 0.0);
-                const double d = xn - x[q];
-                x[q] = xn;
-#pragma unroll
-                for (int q2 = q + 1; q2 < kGS; ++q2)
-                    t[q2] = fma(-(double)Gs[k * RP + b + q2], d, t[q2]);
-            }
-            // Rotate: the next block moves to x[0..kGS).
-            double keep[kGS];
-#pragma unroll
-            for (int q = 0; q < kGS; ++q) keep[q] = x[q];
-#pragma unroll
-            for (int j = 0; j < RP - kGS; ++j) x[j] = x[j + kGS];
-#pragma unroll
-            for (int q = 0; q < kGS; ++q) x[RP - kGS + q] = keep[q];
-        }
-    }
+    const long b = __builtin_amdgcn_update_dpp(0L, __builtin_bit_cast(long, v), 0x150 + Q, 0xf, 0xf,
+                                               false);
+    return __builtin_bit_cast(double, b);
 }
 
 // ------------------------------------------------------------- reductions
@@ -172,48 +87,11 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return t;
 }
 
-// Partial Gram v v^T of the block's 256 rows (FP32 values, FP64 products and
-// sums), written to out (RP*RP), and the block's column maxima max |v_k|,
-// written to out_max (RP). Each wave's 64 rows pass through an LDS tile in
-// turn.
-template <int RP>
-__device__ void block_gram(const float (&v)[RP], double *__restrict__ out,
-                           double *__restrict__ out_max, float (*tile)[RP + 1])
-{
-    constexpr int PER = RP * RP / kThreads;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    double acc[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) acc[q] = 0.0;
-    float cmax = 0.0f;
-    for (int w = 0; w < kThreads / 64; ++w) {
-        if (wave == w) {
-#pragma unroll
-            for (int k = 0; k < RP; ++k) tile[lane][k] = v[k];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + kThreads * q, k = e / RP, l = e % RP;
-            double a = acc[q];
-            for (int row = 0; row < 64; ++row)
-                a = fma((double)tile[row][k], (double)tile[row][l], a);
-            acc[q] = a;
-        }
-        if (tid < RP)
-            for (int row = 0; row < 64; ++row) cmax = fmaxf(cmax, fabsf(tile[row][tid]));
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < PER; ++q) out[tid + kThreads * q] = acc[q];
-    if (tid < RP) out_max[tid] = cmax;
-}
-
 // Marks this block done; returns true in every thread of the last block to
-// finish. Partials written before the call are visible to that block. The
-// blocks of a grid run on all XCDs, whose L2 caches are not coherent with one
+// finish. Writes made before the call are visible to that block. The blocks
+// of a grid run on all XCDs, whose L2 caches are not coherent with one
 // another, so the counter is updated at system scope (coherent at memory);
-// the fences write back and invalidate the L2 for the partials.
+// the fences write back and invalidate the L2 for the data.
 __device__ inline bool last_block(uint32_t *counter, int *s_flag)
 {
     __threadfence();
@@ -236,38 +114,12 @@ __device__ inline void reset_counter(uint32_t *counter)
     __hip_atomic_store(counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Sum of the partial Grams `which` (0 or 1) over nblk blocks in FP64, fixed
-// block order; writes the Gram, its inverse diagonal and the column maxima
-// to G and keeps this thread's Gram entries in g64.
-template <int RP>
-__device__ void finish_gram(const double *__restrict__ part, const double *__restrict__ part_m,
-                            int nblk, int which, double *__restrict__ G, int r,
-                            double (&g64)[RP * RP / kThreads])
-{
-    if (threadIdx.x < RP) {
-        double mx = 0.0;
-        for (int b = 0; b < nblk; ++b) mx = fmax(mx, part_m[((size_t)b * 2 + which) * RP + threadIdx.x]);
-        G[RP * RP + RP + threadIdx.x] = mx;
-    }
-    constexpr int PER = RP * RP / kThreads;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int e = threadIdx.x + kThreads * q;
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[((size_t)b * 2 + which) * RP * RP + e];
-        g64[q] = s;
-        G[e] = s;
-        const int k = e / RP, l = e % RP;
-        if (k == l) G[RP * RP + k] = (k < r && s > 0.0) ? 1.0 / s : 0.0;
-    }
-}
-
 // ------------------------------------------------------ decision (a8 row)
 
 // Error, accept/restart (Algorithm 2) and beta update (Algorithm 3), run by
 // one thread after <W_n, A> (s1) and <W_n^T W_n, H_w H_w^T> (s2) are known.
 __device__ inline void decide(DevState *st, double s1, double s2, double *trace,
-                       uint8_t *accepted, double *beta_used)
+                              uint8_t *accepted, double *beta_used)
 {
     const double e2 = st->nx2 - 2.0 * s1 + s2;               // Remark 1
     const double e = sqrt(e2 > 0.0 ? e2 : 0.0);
@@ -306,20 +158,245 @@ __device__ inline void decide(DevState *st, double s1, double s2, double *trace,
 
 // ------------------------------------------------------------- the kernels
 
-struct SweepArgs {
-    int64_t rows;
-    int r, K, nblk;
-    double *lin;           // nsplit x (rows_pad x RP) partials of the linear term
+struct HalsArgs {
+    int64_t rows;          // factor rows (m for W, n for H^T)
+    int r, K;
+    const double *lin;     // nsplit x (rows_pad x RP) partials of the linear term
     int nsplit;
     int64_t split_stride;
-    float *fac;            // factor slots
+    float *fac;            // factor slots, rows x RP each
     int64_t slot_stride;
-    const double *GW;      // Gram slots of W
-    double *GWout;         // = GW (written by the W side)
-    double *GH;            // Gram of H_w
-    double *part_g;
-    double *part_m;
-    double *part_d;
+    const double *gram;    // Gram buffers of the fixed factor
+    int64_t gram_slot_stride;   // > 0: slot chosen by w_y (H update)
+    double *part;          // per-workgroup records
+    DevState *st;
+};
+
+// SETUP_H / SETUP_W: Gram (and for W, <W0, A>) of slot 0.
+// SWEEP_H (a3 + a4): H_n from H_y by K sweeps with C^T = X^T W_y and
+//   G = W_y^T W_y; H_y' = H_n + beta (H_n - H) (projected for hp = 3); Gram of
+//   H_w (H_n for hp = 1, else H_y').
+// SWEEP_W (a6 + a7): W_n from W_y by K sweeps with A = X H_w^T and
+//   G = H_w H_w^T; W_y' = W_n + beta (W_n - W); <W_n, A>, Gram(W_n),
+//   Gram(W_y').
+template <int RP, int MODE>
+__global__ __launch_bounds__(kThreads, 1) void hals_kernel(HalsArgs a)
+{
+    using MI = ModeInfo<MODE>;
+    constexpr int NB = RP / 16, NS = RP / 4, NG = MI::ngram;
+    constexpr int LREC = rec_len<RP>(NG);
+    static_assert(LREC <= sweep_record(RP), "record fits");
+    constexpr int XLD = RP + 1;                       // padded LDS row (doubles)
+    constexpr int BUF = (kWaves * 16 * XLD > kWaves * NB * 256) ? kWaves * 16 * XLD
+                                                                : kWaves * NB * 256;
+    __shared__ double s_tri[MI::sweeps ? NB : 1][16][16];
+    __shared__ double s_buf[BUF];
+    __shared__ double s_cm[kWaves][NG * RP];
+    __shared__ double s_s1[kWaves];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * kRows + wave * 16;
+
+    DevState *st = a.st;
+    int src = 0, dst_n = 0, dst_y = 0, acc_slot = 0, hp = 3;
+    double beta = 0.0;
+    const double *G = a.gram;
+    if constexpr (MI::sweeps) {
+        if (st->done) return;
+        hp = st->hp;
+        beta = st->beta;
+        if constexpr (MODE == SWEEP_H) {
+            src = st->h_y; dst_n = st->h_n; dst_y = st->h_yn; acc_slot = st->h_acc;
+            G += (int64_t)st->w_y * a.gram_slot_stride;
+        } else {
+            src = st->w_y; dst_n = st->w_n; dst_y = st->w_yn; acc_slot = st->w_acc;
+        }
+    }
+    const float *xsrc = a.fac + src * a.slot_stride;
+
+    // x and c in D layout: rows 4v+g of the wave's tile, coordinate 16b+lr.
+    double xd[NB][4], cd[NB][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + 4 * v + g;
+        const bool ok = row < a.rows;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            xd[b][v] = ok ? (double)xsrc[row * RP + 16 * b + lr] : 0.0;
+            double c = 0.0;
+            if constexpr (MI::lin) {
+                if (ok) {
+                    const double *p = a.lin + row * RP + 16 * b + lr;
+                    c = p[0];
+                    for (int sp = 1; sp < a.nsplit; ++sp) c += p[sp * a.split_stride];
+                }
+            }
+            cd[b][v] = c;
+        }
+    }
+
+    if constexpr (MI::sweeps) {
+        // B operands: -G(4s+g, 16b+lr); inverse diagonal of coordinate 16b+lr;
+        // strictly lower in-block Gram entries, tri[b][q][l] = G(16b+l, 16b+q)
+        // for l > q (0 otherwise), for the in-block corrections.
+        double gb[NS][NB], inv[NB];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) gb[s][b] = -G[(4 * s + g) * RP + 16 * b + lr];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) inv[b] = G[RP * RP + 16 * b + lr];
+        for (int e = tid; e < NB * 256; e += kThreads) {
+            const int b = e >> 8, q = (e >> 4) & 15, l = e & 15;
+            s_tri[b][q][l] = (l > q) ? G[(16 * b + l) * RP + 16 * b + q] : 0.0;
+        }
+        // x in A layout: row lr, coordinate 4s+g.
+        double xa[NS];
+        {
+            const int64_t row = row0 + lr;
+            const bool ok = row < a.rows;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) xa[s] = ok ? (double)xsrc[row * RP + 4 * s + g] : 0.0;
+        }
+        __syncthreads();
+        double *xs = s_buf + wave * 16 * XLD;
+
+        for (int it = 0; it < a.K; ++it) {
+            static_for<NB>([&](auto B) {
+                constexpr int b = decltype(B)::value;
+                // t = c_b - x G(:, b) for the 16 rows and 16 coordinates.
+                double4v t = {cd[b][0], cd[b][1], cd[b][2], cd[b][3]};
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    t = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], gb[s][b], t, 0, 0, 0);
+                // Coordinates 16b .. 16b+15 in order. Every lane forms the
+                // change its coordinate would take; lane q's is the one used
+                // at step q, and the later coordinates correct their t. Lanes
+                // l <= q get a zero correction, so each t stops at the value
+                // its own step used.
+                static_for<16>([&](auto Q) {
+                    constexpr int q = decltype(Q)::value;
+                    const double gq = s_tri[b][q][lr];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const double d = fmax(fma(t[v], inv[b], xd[b][v]), 0.0) - xd[b][v];
+                        t[v] = fma(-gq, row_bcast<q>(d), t[v]);
+                    }
+                });
+#pragma unroll
+                for (int v = 0; v < 4; ++v) xd[b][v] = fmax(fma(t[v], inv[b], xd[b][v]), 0.0);
+                // The block's new values into A layout (wave-private LDS tile;
+                // the LDS operations of a wave complete in order).
+#pragma unroll
+                for (int v = 0; v < 4; ++v) xs[(4 * v + g) * XLD + 16 * b + lr] = xd[b][v];
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int s = 0; s < 4; ++s) xa[4 * b + s] = xs[lr * XLD + 16 * b + 4 * s + g];
+                __builtin_amdgcn_wave_barrier();
+            });
+        }
+    }
+
+    // Epilogue: stored FP32 rows, extrapolation, Gram operands, <x, c>.
+    double gw[NG][NB][4];
+    double s1 = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + 4 * v + g;
+        const bool ok = row < a.rows;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int64_t off = row * RP + 16 * b + lr;
+            const float xn = (float)xd[b][v];
+            if constexpr (MI::sweeps) {
+                float yf = 0.0f;
+                if (ok) {
+                    a.fac[dst_n * a.slot_stride + off] = xn;
+                    const float prev = a.fac[acc_slot * a.slot_stride + off];
+                    double y = fma(beta, (double)xn - (double)prev, (double)xn);
+                    if (MODE == SWEEP_H && hp == 3) y = fmax(y, 0.0);
+                    yf = (float)y;
+                    a.fac[dst_y * a.slot_stride + off] = yf;
+                }
+                if constexpr (MODE == SWEEP_H) {
+                    gw[0][b][v] = ok ? (double)(hp == 1 ? xn : yf) : 0.0;
+                } else {
+                    gw[0][b][v] = ok ? (double)xn : 0.0;
+                    gw[NG - 1][b][v] = ok ? (double)yf : 0.0;
+                }
+            } else {
+                gw[0][b][v] = ok ? (double)xn : 0.0;
+            }
+            if constexpr (MI::s1) s1 = fma((double)xn, cd[b][v], s1);
+        }
+    }
+
+    double *rec = a.part + (size_t)blockIdx.x * LREC;
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+        // Column maxima of the tile: over v, then over the 4 lane groups.
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double mx = 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) mx = fmax(mx, fabs(gw[gi][b][v]));
+            mx = fmax(mx, __shfl_xor(mx, 16));
+            mx = fmax(mx, __shfl_xor(mx, 32));
+            if (g == 0) s_cm[wave][gi * RP + 16 * b + lr] = mx;
+        }
+        // Partial Gram, one block row b1 at a time: G(16b1 + i, 16b2 + j) =
+        // sum over the wave's 16 rows of w(row, 16b1+i) w(row, 16b2+j).
+        static_for<NB>([&](auto B1) {
+            constexpr int b1 = decltype(B1)::value;
+            double4v acc[NB];
+#pragma unroll
+            for (int b2 = 0; b2 < NB; ++b2) {
+                acc[b2] = double4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[b2] = __builtin_amdgcn_mfma_f64_16x16x4f64(gw[gi][b1][v], gw[gi][b2][v],
+                                                                   acc[b2], 0, 0, 0);
+            }
+            __syncthreads();                 // s_buf free (sweep tiles, previous row)
+#pragma unroll
+            for (int b2 = 0; b2 < NB; ++b2)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) s_buf[((wave * NB + b2) * 4 + v) * 64 + lane] = acc[b2][v];
+            __syncthreads();
+            for (int e = tid; e < NB * 256; e += kThreads) {
+                const int b2 = e >> 8, v = (e >> 6) & 3, ln = e & 63;
+                double sum = 0.0;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) sum += s_buf[((w * NB + b2) * 4 + v) * 64 + ln];
+                const int i = 16 * b1 + 4 * v + (ln >> 4), j = 16 * b2 + (ln & 15);
+                rec[gi * (RP * RP + RP) + i * RP + j] = sum;
+            }
+        });
+    }
+    if constexpr (MI::s1) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s1 += __shfl_xor(s1, off);
+        if (lane == 0) s_s1[wave] = s1;
+    }
+    __syncthreads();
+    for (int e = tid; e < NG * RP; e += kThreads) {
+        double mx = s_cm[0][e];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) mx = fmax(mx, s_cm[w][e]);
+        const int gi = e / RP, k = e % RP;
+        rec[gi * (RP * RP + RP) + RP * RP + k] = mx;
+    }
+    if (tid == 0) rec[LREC - 1] = MI::s1 ? ((s_s1[0] + s_s1[1]) + (s_s1[2] + s_s1[3])) : 0.0;
+}
+
+struct FinArgs {
+    const double *part;    // nblk records
+    int nblk, r;
+    double *gram;          // destination Gram buffers
+    int64_t gram_slot_stride;
+    const double *GH;      // Gram of H_w (W sides: s2)
+    double *scratch;       // one double: the summed <x, c>
     uint32_t *counter;
     DevState *st;
     double *trace;
@@ -327,243 +404,147 @@ struct SweepArgs {
     double *beta_used;
 };
 
-// Rounds the FP64 iterate to the FP32 values that are stored.
-template <int RP>
-__device__ __forceinline__ void to_f32(const double (&x)[RP], float (&xf)[RP])
+// Sums the per-workgroup records (16 outputs x 16 block strides per
+// workgroup; the order of every sum is fixed) into the Gram buffers: Gram,
+// inverse diagonal (0 beyond r or for a zero diagonal) and column maxima. The
+// last workgroup then forms e(k) and decides (W sides).
+template <int RP, int MODE>
+__global__ __launch_bounds__(256) void finish_kernel(FinArgs a)
 {
-#pragma unroll
-    for (int k = 0; k < RP; ++k) xf[k] = (float)x[k];
-}
-
-// a3 + a4: H_n from H_y by K sweeps with W_y^T X and W_y^T W_y; H_y' =
-// H_n + beta (H_n - H) (projected for hp = 3); Gram of H_w into GH.
-template <int RP>
-__global__ __launch_bounds__(kThreads) void sweep_h_kernel(SweepArgs a)
-{
-    __shared__ float tile[64][RP + 1];
-    __shared__ int s_last;
-    DevState *st = a.st;
-    if (st->done) return;
-    const int h_acc = st->h_acc, h_y = st->h_y, h_n = st->h_n, h_yn = st->h_yn;
-    const int hp = st->hp;
-    const double beta = st->beta;
-    const double *G = a.GW + (size_t)st->w_y * gram_stride(RP);
-    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-
-    float w[RP];
-    if (j < a.rows) {
-        double x[RP];
-        {
-            float x0[RP];
-            load_row<RP>(a.fac + h_y * a.slot_stride + j * RP, x0);
-#pragma unroll
-            for (int k = 0; k < RP; ++k) x[k] = x0[k];
-        }
-        const double *c = sum_lin<RP>(a.lin, a.nsplit, a.split_stride, j);
-        hals_sweeps<RP>(x, c, G, a.K);
-        float xf[RP], h[RP];
-        to_f32<RP>(x, xf);
-        store_row<RP>(a.fac + h_n * a.slot_stride + j * RP, xf);
-        load_row<RP>(a.fac + h_acc * a.slot_stride + j * RP, h);
-#pragma unroll
-        for (int k = 0; k < RP; ++k) {
-            double y = fma(beta, (double)xf[k] - (double)h[k], (double)xf[k]);
-            if (hp == 3) y = fmax(y, 0.0);
-            h[k] = (float)y;
-        }
-        store_row<RP>(a.fac + h_yn * a.slot_stride + j * RP, h);
-#pragma unroll
-        for (int k = 0; k < RP; ++k) w[k] = (hp == 1) ? xf[k] : h[k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < RP; ++k) w[k] = 0.f;
-    }
-    block_gram<RP>(w, a.part_g + (size_t)blockIdx.x * 2 * RP * RP,
-                   a.part_m + (size_t)blockIdx.x * 2 * RP, tile);
-    if (!last_block(a.counter, &s_last)) return;
-    double g64[RP * RP / kThreads];
-    finish_gram<RP>(a.part_g, a.part_m, a.nblk, 0, a.GH, a.r, g64);
-    if (threadIdx.x == 0) reset_counter(a.counter);
-}
-
-// a6 + a7 + a8: W_n from W_y by K sweeps with X H_w^T and H_w H_w^T;
-// W_y' = W_n + beta (W_n - W); partial <W_n, A>, Gram(W_n), Gram(W_y'); the
-// last block finishes them and takes the decision.
-template <int RP>
-__global__ __launch_bounds__(kThreads) void sweep_w_kernel(SweepArgs a)
-{
-    __shared__ float tile[64][RP + 1];
+    constexpr int NG = ModeInfo<MODE>::ngram;
+    constexpr int GL = RP * RP + RP;
+    constexpr int LREC = rec_len<RP>(NG);
+    __shared__ double sh[16][17];
     __shared__ double shd[4];
     __shared__ int s_last;
     DevState *st = a.st;
-    if (st->done) return;
-    const int w_acc = st->w_acc, w_y = st->w_y, w_n = st->w_n, w_yn = st->w_yn;
-    const double beta = st->beta;
-    const double *G = a.GH;
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-
-    float xf[RP], y[RP];
-    double s1 = 0.0;
-    if (i < a.rows) {
-        double x[RP];
-        {
-            float x0[RP];
-            load_row<RP>(a.fac + w_y * a.slot_stride + i * RP, x0);
-#pragma unroll
-            for (int k = 0; k < RP; ++k) x[k] = x0[k];
+    int slot[NG];
+    if constexpr (MODE == SWEEP_H || MODE == SWEEP_W) {
+        if (st->done) return;
+    }
+    if constexpr (MODE == SWEEP_W) {
+        slot[0] = st->w_n;
+        slot[NG - 1] = st->w_yn;
+    } else {
+        slot[0] = 0;
+    }
+    const int o = threadIdx.x & 15, j = threadIdx.x >> 4;
+    const int e = blockIdx.x * 16 + o;
+    const bool is_max = e < NG * GL && (e % GL) >= RP * RP;
+    double v = 0.0;
+    if (e < LREC) {
+        for (int b = j; b < a.nblk; b += 16) {
+            const double x = a.part[(size_t)b * LREC + e];
+            v = is_max ? fmax(v, x) : v + x;
         }
-        const double *c = sum_lin<RP>(a.lin, a.nsplit, a.split_stride, i);
-        hals_sweeps<RP>(x, c, G, a.K);
-        to_f32<RP>(x, xf);
-        store_row<RP>(a.fac + w_n * a.slot_stride + i * RP, xf);
-        s1 = dot_lin<RP>(xf, c);
-        load_row<RP>(a.fac + w_acc * a.slot_stride + i * RP, y);
-#pragma unroll
-        for (int k = 0; k < RP; ++k)
-            y[k] = (float)fma(beta, (double)xf[k] - (double)y[k], (double)xf[k]);
-        store_row<RP>(a.fac + w_yn * a.slot_stride + i * RP, y);
-    } else {
-#pragma unroll
-        for (int k = 0; k < RP; ++k) { xf[k] = 0.f; y[k] = 0.f; }
     }
-    double *pb = a.part_g + (size_t)blockIdx.x * 2 * RP * RP;
-    double *pm = a.part_m + (size_t)blockIdx.x * 2 * RP;
-    block_gram<RP>(xf, pb, pm, tile);
-    block_gram<RP>(y, pb + RP * RP, pm + RP, tile);
-    s1 = block_sum(s1, shd);
-    if (threadIdx.x == 0) a.part_d[blockIdx.x] = s1;
-    if (!last_block(a.counter, &s_last)) return;
-
-    double gn[RP * RP / kThreads], gy[RP * RP / kThreads];
-    finish_gram<RP>(a.part_g, a.part_m, a.nblk, 0, a.GWout + (size_t)w_n * gram_stride(RP), a.r, gn);
-    finish_gram<RP>(a.part_g, a.part_m, a.nblk, 1, a.GWout + (size_t)w_yn * gram_stride(RP), a.r, gy);
-    double s2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < RP * RP / kThreads; ++q)
-        s2 = fma(gn[q], a.GH[threadIdx.x + kThreads * q], s2);
-    s2 = block_sum(s2, shd);
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int b = 0; b < a.nblk; ++b) t += a.part_d[b];
-        decide(st, t, s2, a.trace, a.accepted, a.beta_used);
-        reset_counter(a.counter);
-    }
-}
-
-// Set-up: Gram of the rows of slot 0 of `fac` into Gout. With `with_error`
-// (W side) it also forms <W0, A> and, in the last block, e(0) (Alg. 2, first
-// step, via Remark 1) and the initial state.
-template <int RP>
-__global__ __launch_bounds__(kThreads) void setup_gram_kernel(SweepArgs a, int with_error)
-{
-    __shared__ float tile[64][RP + 1];
-    __shared__ double shd[4];
-    __shared__ int s_last;
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    float x[RP];
-    double s1 = 0.0;
-    if (i < a.rows) {
-        load_row<RP>(a.fac + i * RP, x);
-        if (with_error) s1 = dot_lin<RP>(x, sum_lin<RP>(a.lin, a.nsplit, a.split_stride, i));
-    } else {
-#pragma unroll
-        for (int k = 0; k < RP; ++k) x[k] = 0.f;
-    }
-    block_gram<RP>(x, a.part_g + (size_t)blockIdx.x * 2 * RP * RP,
-                   a.part_m + (size_t)blockIdx.x * 2 * RP, tile);
-    if (with_error) {
-        s1 = block_sum(s1, shd);
-        if (threadIdx.x == 0) a.part_d[blockIdx.x] = s1;
+    sh[j][o] = v;
+    __syncthreads();
+    if (j == 0 && e < LREC) {
+        double s = sh[0][o];
+        for (int q = 1; q < 16; ++q) s = is_max ? fmax(s, sh[q][o]) : s + sh[q][o];
+        if (e < NG * GL) {
+            const int gi = e / GL, w = e % GL;
+            double *Gd = a.gram + slot[gi] * a.gram_slot_stride;
+            if (w < RP * RP) {
+                Gd[w] = s;
+                const int k = w / RP, l = w % RP;
+                if (k == l) Gd[RP * RP + k] = (k < a.r && s > 0.0) ? 1.0 / s : 0.0;
+            } else {
+                Gd[RP * RP + RP + (w - RP * RP)] = s;
+            }
+        } else if (ModeInfo<MODE>::s1) {
+            a.scratch[0] = s;
+        }
     }
     if (!last_block(a.counter, &s_last)) return;
-    double g[RP * RP / kThreads];
-    finish_gram<RP>(a.part_g, a.part_m, a.nblk, 0, a.GWout, a.r, g);
-    if (with_error) {
+    if constexpr (ModeInfo<MODE>::s1) {
+        const double *Gn = a.gram + slot[0] * a.gram_slot_stride;
         double s2 = 0.0;
-#pragma unroll
-        for (int q = 0; q < RP * RP / kThreads; ++q)
-            s2 = fma(g[q], a.GH[threadIdx.x + kThreads * q], s2);
+        for (int q = threadIdx.x; q < RP * RP; q += 256) s2 = fma(Gn[q], a.GH[q], s2);
         s2 = block_sum(s2, shd);
         if (threadIdx.x == 0) {
-            DevState *st = a.st;
-            double t = 0.0;
-            for (int b = 0; b < a.nblk; ++b) t += a.part_d[b];
-            const double e2 = st->nx2 - 2.0 * t + s2;
-            const double e = sqrt(e2 > 0.0 ? e2 : 0.0);
-            a.trace[0] = e / sqrt(st->nx2);
-            st->e0 = e;
-            st->e_prev = e;
-            st->e_acc = e;
-            if (!isfinite(e) || st->max_iter == 0) st->done = 1;
+            const double s1 = a.scratch[0];
+            if constexpr (MODE == SWEEP_W) {
+                decide(st, s1, s2, a.trace, a.accepted, a.beta_used);
+            } else {
+                // e(0) of Algorithm 2 through Remark 1.
+                const double e2 = st->nx2 - 2.0 * s1 + s2;
+                const double e0 = sqrt(e2 > 0.0 ? e2 : 0.0);
+                a.trace[0] = e0 / sqrt(st->nx2);
+                st->e0 = e0;
+                st->e_prev = e0;
+                st->e_acc = e0;
+                if (!isfinite(e0) || st->max_iter == 0) st->done = 1;
+            }
         }
     }
     if (threadIdx.x == 0) reset_counter(a.counter);
 }
 
-template <int RP>
-SweepArgs base_args(const Buffers &b, int64_t rows, int r, int K)
-{
-    SweepArgs a{};
-    a.rows = rows;
-    a.r = r;
-    a.K = K;
-    a.nblk = (int)((rows + kThreads - 1) / kThreads);
-    a.part_g = b.part_g;
-    a.part_m = b.part_m;
-    a.part_d = b.part_d;
-    a.st = b.st;
-    a.trace = b.trace;
-    a.accepted = b.accepted;
-    a.beta_used = b.beta_used;
-    a.GW = b.GW;
-    a.GWout = b.GW;
-    a.GH = b.GH;
-    return a;
-}
-
-// Enqueues the sweep kernels of one padded rank (one translation unit each).
+// Enqueues one half-iteration (or a set-up step) of one padded rank.
 template <int RP>
 struct Launch {
+    template <int MODE>
+    static void run(int64_t rows, int r, int K, const Buffers &b, bool w_side, uint32_t *counter,
+                    hipStream_t s)
+    {
+        constexpr int NG = ModeInfo<MODE>::ngram;
+        HalsArgs h{};
+        h.rows = rows;
+        h.r = r;
+        h.K = K;
+        h.fac = w_side ? b.Wf : b.Hf;
+        h.slot_stride = rows * RP;
+        if (w_side) {
+            h.lin = b.A;
+            h.nsplit = b.nsplit_a;
+            h.split_stride = b.m_pad * RP;
+            h.gram = b.GH;
+            h.gram_slot_stride = 0;
+        } else {
+            h.lin = b.Ct;
+            h.nsplit = b.nsplit_c;
+            h.split_stride = b.n_pad * RP;
+            h.gram = b.GW;
+            h.gram_slot_stride = gram_stride(RP);
+        }
+        h.part = b.part_g;
+        h.st = b.st;
+        const int nblk = (int)((rows + kRows - 1) / kRows);
+        hals_kernel<RP, MODE><<<nblk, kThreads, 0, s>>>(h);
+
+        FinArgs f{};
+        f.part = b.part_g;
+        f.nblk = nblk;
+        f.r = r;
+        f.gram = w_side ? b.GW : b.GH;
+        f.gram_slot_stride = w_side ? gram_stride(RP) : 0;
+        f.GH = b.GH;
+        f.scratch = b.part_d;
+        f.counter = counter;
+        f.st = b.st;
+        f.trace = b.trace;
+        f.accepted = b.accepted;
+        f.beta_used = b.beta_used;
+        const int fblk = (rec_len<RP>(NG) + 15) / 16;
+        finish_kernel<RP, MODE><<<fblk, 256, 0, s>>>(f);
+    }
     static void sweep_h(int64_t n, int r, int K, const Buffers &b, hipStream_t s)
     {
-        SweepArgs a = base_args<RP>(b, n, r, K);
-        a.lin = b.Ct;
-        a.nsplit = b.nsplit_c;
-        a.split_stride = b.n_pad * RP;
-        a.fac = b.Hf;
-        a.slot_stride = n * RP;
-        a.counter = b.counters + CNT_H;
-        sweep_h_kernel<RP><<<a.nblk, kThreads, 0, s>>>(a);
+        run<SWEEP_H>(n, r, K, b, false, b.counters + CNT_H, s);
     }
     static void sweep_w(int64_t m, int r, int K, const Buffers &b, hipStream_t s)
     {
-        SweepArgs a = base_args<RP>(b, m, r, K);
-        a.lin = b.A;
-        a.nsplit = b.nsplit_a;
-        a.split_stride = b.m_pad * RP;
-        a.fac = b.Wf;
-        a.slot_stride = m * RP;
-        a.counter = b.counters + CNT_W;
-        sweep_w_kernel<RP><<<a.nblk, kThreads, 0, s>>>(a);
+        run<SWEEP_W>(m, r, K, b, true, b.counters + CNT_W, s);
     }
     static void setup_h(int64_t n, int r, const Buffers &b, hipStream_t s)
     {
-        SweepArgs a = base_args<RP>(b, n, r, 0);
-        a.fac = b.Hf;
-        a.GWout = b.GH;
-        a.counter = b.counters + CNT_G;
-        setup_gram_kernel<RP><<<a.nblk, kThreads, 0, s>>>(a, 0);
+        run<SETUP_H>(n, r, 0, b, false, b.counters + CNT_G, s);
     }
     static void setup_err(int64_t m, int r, const Buffers &b, hipStream_t s)
     {
-        SweepArgs a = base_args<RP>(b, m, r, 0);
-        a.fac = b.Wf;
-        a.lin = b.A;
-        a.nsplit = b.nsplit_a;
-        a.split_stride = b.m_pad * RP;
-        a.GWout = b.GW;   // slot 0
-        a.counter = b.counters + CNT_G;
-        setup_gram_kernel<RP><<<a.nblk, kThreads, 0, s>>>(a, 1);
+        run<SETUP_W>(m, r, 0, b, true, b.counters + CNT_G, s);
     }
 };
 
