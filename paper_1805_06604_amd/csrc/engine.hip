@@ -79,8 +79,9 @@ int choose_kernel(const nmf_params *p)
     }
 }
 
-// Split-K plan of one product: enough workgroups to fill the chip (about 512
-// of 128 rows each), K-chunks of whole 64-column tiles.
+// Split-K plan of one product: enough workgroups of 128 rows to fill the chip
+// (about 512 for the kernels that run two per CU, 256 for the exact-integer
+// kernel, whose LDS ring takes a whole CU), K-chunks of whole 64-column tiles.
 void plan_product(nmf::ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, int64_t K,
                   int64_t ld)
 {
@@ -94,7 +95,8 @@ void plan_product(nmf::ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, 
         return;
     }
     const int64_t rb = rows_pad / 128, tiles = ld / 64;
-    int64_t want = (512 + rb - 1) / rb;
+    const int64_t target = (kernel == nmf::PK_MFMA_I8) ? 256 : 512;
+    int64_t want = (target + rb - 1) / rb;
     // The exact-integer sums stay below 2^31 for chunks of at most 65536.
     if (kernel == nmf::PK_MFMA_I8) want = std::max<int64_t>(want, (tiles + 1023) / 1024);
     want = std::max<int64_t>(1, std::min<int64_t>({want, tiles, 64}));
@@ -159,7 +161,7 @@ void free_all(nmf_ctx *c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     void *ptrs[] = {c->X, c->Xt, c->zexp_x, c->zexp_xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH,
                     c->b.A, c->b.Ct, c->b.part_g, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
-                    c->b.accepted, c->b.beta_used, c->b.stage};
+                    c->b.accepted, c->b.beta_used, c->b.stage, c->b.fsl, c->b.texp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -196,6 +198,12 @@ nmf_status alloc_buffers(nmf_ctx *c)
     HIP_TRY(c, dalloc(&b.accepted, (size_t)c->p.max_iter));
     HIP_TRY(c, dalloc(&b.beta_used, (size_t)c->p.max_iter));
     HIP_TRY(c, dalloc(&b.stage, (size_t)(m + n) * c->r));
+    if (c->prod_kernel == nmf::PK_MFMA_I8) {
+        // Both products slice their factor into one shared buffer (they run in
+        // stream order): (ld / 64) tiles of 4 slices x RP columns x 64 rows.
+        HIP_TRY(c, dalloc(&b.fsl, (size_t)std::max(c->ldx, c->ldxt) * 4 * rp));
+        HIP_TRY(c, dalloc(&b.texp, (size_t)rp));
+    }
     // Zero the factor slots once so that no slot ever holds garbage padding.
     HIP_TRY(c, hipMemset(b.Wf, 0, sizeof(float) * nmf::kSlots * m * rp));
     HIP_TRY(c, hipMemset(b.Hf, 0, sizeof(float) * nmf::kSlots * n * rp));
@@ -356,6 +364,8 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
         c->pa.zexp = c->zexp_x;
         c->pa.gram_base = c->b.GH;
         c->pa.gram_slot_stride = 0;
+        c->pa.Fsl = c->b.fsl;
+        c->pa.texp = c->b.texp;
         c->pc.Z = c->Xt;
         c->pc.F_base = c->b.Wf;
         c->pc.slot_stride = c->m * c->rp;
@@ -364,6 +374,8 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
         c->pc.zexp = c->zexp_xt;
         c->pc.gram_base = c->b.GW;
         c->pc.gram_slot_stride = nmf::gram_stride(c->rp);
+        c->pc.Fsl = c->b.fsl;
+        c->pc.texp = c->b.texp;
     }
     if (st == NMF_OK && !(c->nx2 > 0.0))
         st = fail(c, NMF_E_INVAL, "X is zero: the relative error is undefined");

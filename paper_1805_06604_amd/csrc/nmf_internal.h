@@ -82,6 +82,8 @@ struct ProdArgs {
     const int *zexp;
     const double *gram_base;
     int64_t gram_slot_stride;
+    signed char *Fsl;       // the factor in int8 slices: (ld / 64) x 4 x RP x 64
+    int *texp;              // its column scale exponents (RP)
 };
 
 // Product kernels: VALU FP64 FMA over FP32 operands (products exact, sums in
@@ -112,6 +114,8 @@ struct Buffers {
     uint8_t *accepted = nullptr;
     double *beta_used = nullptr;
     float *stage = nullptr;  // staging of W0 / H0 / outputs: (m + n) * r
+    signed char *fsl = nullptr; // exact-integer products: the sliced factor (shared)
+    int *texp = nullptr;     // and its column exponents
 };
 
 // Last-block counters, one per kernel kind, each on its own 256-byte line.

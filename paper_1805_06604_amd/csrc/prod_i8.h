@@ -15,11 +15,19 @@
 // products accurate to about 2^-27 of the row and column maxima, with no
 // rounding in the summation over K.
 //
+// Z layout (fragment order). The slices of Z are stored per 16-row block and
+// 64-column tile as 4 slices x 64 lanes x 16 bytes, lane lr + 16 g holding
+// row lr, columns 16 g .. 16 g + 15 of the tile: [row / 16][tile][slice]
+// [lane][16]. One wave load of an MFMA operand is then 1 KB of contiguous
+// memory, and a 16-row block streams its K-chunk front to back.
+//
 // Tiling. A workgroup is 4 waves over 128 rows x RP columns and one K-chunk;
 // each wave owns 32 rows (two 16-row MFMA blocks) and all RP/16 column blocks.
 // K advances in tiles of 64 (one MFMA k-step). The slices of Z go straight
-// from HBM to registers, one tile ahead; the FP32 factor tile is sliced once
-// per workgroup into LDS in MFMA operand order.
+// through a 3-stage LDS ring filled by direct global-to-LDS loads, two tiles
+// ahead of the multiply, one barrier per tile; the factor is sliced once per
+// product by its own kernel (in MFMA operand order) and each tile of it rides
+// in the same ring stage as the Z tile.
 #pragma once
 
 #include "nmf_internal.h"
@@ -35,7 +43,6 @@ constexpr int kBM = kWaves * kWM;       // rows per workgroup
 constexpr int kKT = 64;                 // K per tile (one MFMA k-step)
 constexpr int kSl = 4;                  // slices per value
 constexpr int kMaxW = 3;                // kept pairs: a + b <= kMaxW
-constexpr int kLdsRow = kKT + 16;       // LDS bytes per factor column (padded)
 
 // Scale exponent s with |x| 2^s < 64 for |x| <= amax (0 for amax == 0).
 __host__ __device__ inline int slice_exponent(double amax)
@@ -57,13 +64,20 @@ __device__ __forceinline__ void slice4(float u, int (&d)[kSl])
     }
 }
 
-template <int RP>
-__global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
-{
-    constexpr int NCB = RP / 16;
-    __shared__ __attribute__((aligned(16))) signed char Fs[kSl][RP][kLdsRow];
-    __shared__ int s_texp[RP];
+// Position of the 16-byte part `part` (columns 16 part .. 16 part + 15 of the
+// tile) of factor column c in a sliced tile: parts are XOR-swizzled by
+// (c / 4) mod 4, so that the 16 lanes reading one part of 16 consecutive
+// columns hit distinct LDS banks.
+__host__ __device__ constexpr int fpart(int c, int part) { return part ^ ((c >> 2) & 3); }
 
+// Slices one 64-row tile of the factor F (K x RP, FP32) per workgroup into
+// Fsl[tile][slice][column][4 parts of 16] (int8, MFMA operand order, parts
+// swizzled by fpart, zero past K), with column exponents t_k from the column
+// maxima; block 0 also stores t_k.
+template <int RP>
+__global__ __launch_bounds__(256) void slice_factor_kernel(ProdArgs a)
+{
+    __shared__ int s_texp[RP];
     const DevState *st = a.st;
     int slot = 0;
     if (a.sel != SEL_SLOT0) {
@@ -73,11 +87,65 @@ __global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
     const float *__restrict__ F = a.F_base + slot * a.slot_stride;
     const double *colmax = (a.sel == SEL_W_Y ? a.gram_base + (size_t)st->w_y * a.gram_slot_stride
                                              : a.gram_base) + RP * RP + RP;
+    const int tid = threadIdx.x;
+    if (tid < RP) {
+        s_texp[tid] = slice_exponent(colmax[tid]);
+        if (blockIdx.x == 0) a.texp[tid] = s_texp[tid];
+    }
+    __syncthreads();
+    const int64_t tile = blockIdx.x;
+    uint32_t *out = reinterpret_cast<uint32_t *>(a.Fsl + tile * (kSl * RP * kKT));
+    for (int item = tid; item < RP * (kKT / 4); item += 256) {
+        const int c = item % RP, kq = item / RP;
+        uint32_t w[kSl] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t k = tile * kKT + 4 * kq + e;
+            const float f = (k < a.K) ? F[k * RP + c] : 0.0f;
+            int d[kSl];
+            slice4(ldexpf(f, s_texp[c]), d);
+#pragma unroll
+            for (int p = 0; p < kSl; ++p) w[p] |= ((uint32_t)(d[p] & 0xff)) << (8 * e);
+        }
+#pragma unroll
+        for (int p = 0; p < kSl; ++p)
+            out[(p * RP + c) * (kKT / 4) + fpart(c, kq / 4) * 4 + kq % 4] = w[p];
+    }
+}
+
+// Direct global-to-LDS copy of `bytes` contiguous bytes (a multiple of 4 KB)
+// by one wave: 1 KB per instruction, lane l moving bytes 16 l .. 16 l + 15.
+template <int BYTES>
+__device__ __forceinline__ void dma_wave(signed char *lds, const signed char *src, int lane)
+{
+#pragma unroll
+    for (int q = 0; q < BYTES / 1024; ++q)
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void *)(src + q * 1024 + 16 * lane),
+            (__attribute__((address_space(3))) void *)(lds + q * 1024), 16, 0, 0);
+}
+
+// Stages of the LDS ring: tile t lives in stage t mod kStages; two tiles are
+// in flight while one is multiplied.
+constexpr int kStages = 3;
+
+template <int RP>
+__global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
+{
+    constexpr int NCB = RP / 16;
+    constexpr int FT = kSl * RP * kKT;                // factor tile bytes
+    constexpr int ZW = 2 * kSl * 1024;                // Z bytes of one wave per tile
+    constexpr int STAGE = kWaves * ZW + FT;           // [Z of waves 0..3][factor tile]
+    constexpr int FW = FT / kWaves;                   // factor bytes moved per wave
+    constexpr int OPS = (ZW + FW) / 1024;             // direct loads per wave per tile
+    static_assert(FW % 1024 == 0 && OPS <= 15, "tile splits evenly; vmcnt fits");
+    __shared__ __attribute__((aligned(1024))) signed char ring[kStages][STAGE];
+
+    const DevState *st = a.st;
+    if (a.sel != SEL_SLOT0 && st->done) return;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, lr = lane & 15;
-    if (tid < RP) s_texp[tid] = slice_exponent(colmax[tid]);
-
     const int kc = blockIdx.x % a.nsplit;
     const int64_t rb = blockIdx.x / a.nsplit;
     const int64_t kbeg = (int64_t)kc * a.kchunk;
@@ -85,10 +153,14 @@ __global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
     if (kend > a.ld) kend = a.ld;
     const int64_t row0 = rb * kBM + wave * kWM;
     const int64_t ntile = a.ld / kKT;
-    // Z slices: [row][tile][slice][64 bytes]; lane group g reads bytes 16g..16g+15.
+    // The wave's two 16-row blocks are adjacent in the fragment layout only
+    // tile by tile: block b of tile t starts at ((row0/16 + b) ntile + t) 4 KB.
     const signed char *Z = static_cast<const signed char *>(a.Z);
-    const signed char *zr0 = Z + ((row0 + lr) * ntile) * (kSl * kKT) + 16 * g;
-    const signed char *zr1 = Z + ((row0 + 16 + lr) * ntile) * (kSl * kKT) + 16 * g;
+    const signed char *zsrc0 = Z + (row0 / 16) * ntile * (kSl * 1024);
+    const signed char *zsrc1 = zsrc0 + ntile * (kSl * 1024);
+    // This lane's byte offset of part g of column 16 c + lr, slice j, within
+    // the factor tile: ((j RP + 16 c + lr) 4 + fpart) 16.
+    const int boff = (lr * 4 + fpart(lr, g)) * 16;
 
     int32x4 acc[2][NCB][kMaxW + 1];
 #pragma unroll
@@ -98,89 +170,63 @@ __global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
 #pragma unroll
             for (int w = 0; w <= kMaxW; ++w) acc[b][c][w] = int32x4{0, 0, 0, 0};
 
-    // Factor tile loader: KT x RP FP32 values as float4 chunks.
-    constexpr int CHUNKS = kKT * RP / 4;
-    constexpr int PER_T = (CHUNKS + kWaves * 64 - 1) / (kWaves * 64);
-    float4 fpre[PER_T];
-    auto load_f = [&](int64_t k0) {
-#pragma unroll
-        for (int i = 0; i < PER_T; ++i) {
-            const int q = tid + i * kWaves * 64;
-            const int kk = q / (RP / 4), c4 = (q % (RP / 4)) * 4;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (q < CHUNKS && k0 + kk < a.K)
-                v = *reinterpret_cast<const float4 *>(F + (k0 + kk) * RP + c4);
-            fpre[i] = v;
-        }
+    const int64_t t0 = kbeg / kKT, t1 = (kend + kKT - 1) / kKT;   // tiles [t0, t1)
+    // Issues the direct loads of tile `tile` into stage `sg` (OPS per wave).
+    auto issue = [&](int64_t tile, int sg) {
+        signed char *base = ring[sg];
+        dma_wave<kSl * 1024>(base + wave * ZW, zsrc0 + tile * (kSl * 1024), lane);
+        dma_wave<kSl * 1024>(base + wave * ZW + kSl * 1024, zsrc1 + tile * (kSl * 1024), lane);
+        dma_wave<FW>(base + kWaves * ZW + wave * FW, a.Fsl + tile * FT + wave * FW, lane);
     };
-    auto store_f = [&]() {
-#pragma unroll
-        for (int i = 0; i < PER_T; ++i) {
-            const int q = tid + i * kWaves * 64;
-            if (q >= CHUNKS) continue;
-            const int kk = q / (RP / 4), c4 = (q % (RP / 4)) * 4;
-            const float v[4] = {fpre[i].x, fpre[i].y, fpre[i].z, fpre[i].w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int d[kSl];
-                slice4(ldexpf(v[e], s_texp[c4 + e]), d);
-#pragma unroll
-                for (int p = 0; p < kSl; ++p) Fs[p][c4 + e][kk] = (signed char)d[p];
-            }
-        }
-    };
-
-    int32x4 zcur[2][kSl], znext[2][kSl];
-    auto load_z = [&](int64_t tile, int32x4 (&z)[2][kSl]) {
-#pragma unroll
-        for (int p = 0; p < kSl; ++p) {
-            z[0][p] = *reinterpret_cast<const int32x4 *>(zr0 + tile * (kSl * kKT) + p * kKT);
-            z[1][p] = *reinterpret_cast<const int32x4 *>(zr1 + tile * (kSl * kKT) + p * kKT);
-        }
-    };
-
-    __syncthreads();   // s_texp
-    if (kbeg < kend) {
-        load_z(kbeg / kKT, zcur);
-        load_f(kbeg);
+    if (t0 < t1) {
+        issue(t0, 0);
+        issue(t0 + 1 < t1 ? t0 + 1 : t0, 1);
     }
-    for (int64_t k0 = kbeg; k0 < kend; k0 += kKT) {
-        __syncthreads();            // the previous tile's LDS reads are done
-        store_f();
-        const bool more = k0 + kKT < kend;
-        if (more) {
-            load_z(k0 / kKT + 1, znext);
-            load_f(k0 + kKT);
-        }
-        __syncthreads();
-        int32x4 bp[NCB][kSl];
+    int sg = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        // Tile t's loads (issued before the OPS loads of tile t + 1) have
+        // landed; after the barrier every wave's share is visible and every
+        // wave is done with the stage read in the previous iteration.
+        __builtin_amdgcn_s_waitcnt(0x0070 | OPS);     // vmcnt(OPS) lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        // Tile t + 2 (or a harmless reload of the last tile) into the stage
+        // freed by tile t - 1.
+        const int sn = (sg + 2 >= kStages) ? sg + 2 - kStages : sg + 2;
+        issue(t + 2 < t1 ? t + 2 : t1 - 1, sn);
+        const signed char *zt = ring[sg] + wave * ZW + 16 * lane;
+        const signed char *ft = ring[sg] + kWaves * ZW;
+        int32x4 z[2][kSl];
 #pragma unroll
-        for (int c = 0; c < NCB; ++c)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int p = 0; p < kSl; ++p)
-                bp[c][p] = *reinterpret_cast<const int32x4 *>(&Fs[p][c * 16 + lr][16 * g]);
-        // Consecutive MFMAs cycle through the 2 x NCB output blocks.
+                z[b][p] = *reinterpret_cast<const int32x4 *>(zt + (b * kSl + p) * 1024);
+        // Factor slice j against Z slices i <= kMaxW - j; consecutive MFMAs
+        // cycle through the 2 x NCB output blocks.
 #pragma unroll
-        for (int i = 0; i < kSl; ++i)
+        for (int j = 0; j < kSl; ++j) {
+            int32x4 bp[NCB];
 #pragma unroll
-            for (int j = 0; j < kSl; ++j)
-                if (i + j <= kMaxW)
+            for (int c = 0; c < NCB; ++c)
+                bp[c] = *reinterpret_cast<const int32x4 *>(ft + (j * RP + 16 * c) * 64 + boff);
 #pragma unroll
-                    for (int b = 0; b < 2; ++b)
+            for (int i = 0; i + j <= kMaxW; ++i)
 #pragma unroll
-                        for (int c = 0; c < NCB; ++c)
-                            acc[b][c][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                                zcur[b][i], bp[c][j], acc[b][c][i + j], 0, 0, 0);
-        if (more) {
+                for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int p = 0; p < kSl; ++p) zcur[b][p] = znext[b][p];
+                    for (int c = 0; c < NCB; ++c)
+                        acc[b][c][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            z[b][i], bp[c], acc[b][c][i + j], 0, 0, 0);
         }
+        sg = (sg + 1 == kStages) ? 0 : sg + 1;
     }
+    __builtin_amdgcn_s_waitcnt(0x0070);                // vmcnt(0): no load outlives the loop
 
     // D layout: lane holds column lr of each block, rows 4g..4g+3.
     double *Y = a.Y + (size_t)kc * a.rows_pad * RP;
+    int te[NCB];
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) te[c] = a.texp[c * 16 + lr];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
 #pragma unroll
@@ -192,7 +238,7 @@ __global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
                 double v = 0.0;
 #pragma unroll
                 for (int w = kMaxW; w >= 0; --w) v = v * (1.0 / 128.0) + (double)acc[b][c][w][i];
-                Y[row * RP + c * 16 + lr] = ldexp(v, -se - s_texp[c * 16 + lr]);
+                Y[row * RP + c * 16 + lr] = ldexp(v, -se - te[c]);
             }
         }
     }
@@ -201,6 +247,7 @@ __global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
 template <int RP>
 void launch(const ProdArgs &a, hipStream_t s)
 {
+    slice_factor_kernel<RP><<<(unsigned)(a.ld / kKT), 256, 0, s>>>(a);
     const int64_t blocks = (a.rows_pad / kBM) * a.nsplit;
     prod_i8_kernel<RP><<<(unsigned)blocks, kWaves * 64, 0, s>>>(a);
 }

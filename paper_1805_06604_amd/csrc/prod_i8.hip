@@ -14,8 +14,9 @@ __device__ __forceinline__ float as_f32(__hip_bfloat16 v) { return __bfloat162fl
 __device__ __forceinline__ float as_f32(__half v) { return __half2float(v); }
 
 // One workgroup per row of Z: the row's max |z|, its scale exponent, then the
-// four slices of every entry in [row][tile][slice][64] order. Entries past
-// `cols` (row padding) are zero.
+// four slices of every entry in fragment order ([row / 16][tile][slice][lane]
+// [16], lane = row % 16 + 16 (column % 64) / 16). Entries past `cols` (row
+// padding) are zero.
 template <typename XT>
 __global__ __launch_bounds__(256) void slice_rows_kernel(const XT *__restrict__ src, int64_t cols,
                                                          int64_t ld_src, int64_t ntile,
@@ -33,14 +34,15 @@ __global__ __launch_bounds__(256) void slice_rows_kernel(const XT *__restrict__ 
     mx = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
     const int s = slice_exponent(mx);
     if (threadIdx.x == 0) zexp[row] = s;
-    signed char *out = dst + row * ntile * (kSl * kKT);
+    signed char *out = dst + (row / 16) * ntile * (kSl * 1024) + (row % 16) * 16;
     for (int64_t j = threadIdx.x; j < ntile * kKT; j += 256) {
         const float x = (j < cols) ? as_f32(z[j]) : 0.0f;
         int d[kSl];
         slice4(ldexpf(x, s), d);
         const int64_t t = j / kKT, kk = j % kKT;
 #pragma unroll
-        for (int p = 0; p < kSl; ++p) out[(t * kSl + p) * kKT + kk] = (signed char)d[p];
+        for (int p = 0; p < kSl; ++p)
+            out[(t * kSl + p) * 1024 + (kk / 16) * 256 + (kk % 16)] = (signed char)d[p];
     }
 }
 
