@@ -5,12 +5,18 @@ both HALS sweep blocks with their epilogues, the FP64 decision). The default
 workload is the planted dense 16384 x 16384, r = 64 problem (X = W H +
 1e-3 |N(0,1)|, seeded); X, W and H are resident in HBM before timing starts.
 
-Prints one JSON line. `value` is outer iterations per second. `roofline`
-covers the dominant kernel (the X-streaming product; both products of an
-iteration are launches of that kernel), timed with HIP events on the stream
-the library launches it on. `cpu_baseline` times the FP64 oracle on a
-bounded sample of the same workload and scales it by the iteration's flop
-count to the full size.
+Prints one JSON line. `value` is outer iterations per second over the timed
+graph launches. `roofline` covers the dominant kernel (the X-streaming
+product; both products of an iteration are launches of that kernel): its
+algorithmic bytes per launch over its mean duration, timed with HIP events
+recorded around each launch on the stream the library launches it on, over
+`--profile-iters` iterations run right after the timed ones. `cpu_baseline`
+times the FP64 oracle on a bounded sample of the same workload and scales it
+by the iteration's flop count to the full size.
+
+--copy-calib runs torch's plain device copy of 1 GiB a few times first: the
+reference kernel for scaling the HBM byte counters (FETCH_SIZE, WRITE_SIZE)
+of a profiler run.
 """
 import argparse
 import hashlib
@@ -26,8 +32,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "E-A-HALS iters/s + HBM GB/s at 16384² r=64; batched solves/s, p99 latency"
 HBM_PEAK_GBS = 8000.0
-PRODUCT_SOURCES = ["paper_1805_06604_amd/csrc/kernels_dense.hip",
-                   "paper_1805_06604_amd/csrc/prod_mfma.h"]
+PRODUCT_SOURCES = ["paper_1805_06604_amd/csrc/prod_i8.h",
+                   "paper_1805_06604_amd/csrc/prod_i8.hip",
+                   "paper_1805_06604_amd/csrc/prod_mfma.h",
+                   "paper_1805_06604_amd/csrc/kernels_dense.hip"]
 XBYTES = {"f32": 4, "bf16": 2, "f16": 2}
 
 
@@ -46,6 +54,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2048,
                     help="m = n of the oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run the 1 GiB reference copy (counter calibration) first")
     return ap.parse_args()
 
 
@@ -116,6 +126,13 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_calib:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     m, n, r, K = args.m, args.n, args.r, args.inner_k
     p = S.planted(0, m=m, n=n, r=r)
     total = args.warmup + args.steps + args.profile_iters
@@ -145,9 +162,12 @@ def main():
     solver.close()
 
     sx = XBYTES[args.x_dtype]
-    prod_bytes = m * n * sx + (m + n) * r * 4
-    prod_ms = 0.5 * (phases["prod_xt_w"] + phases["prod_x_h"])
-    achieved = prod_bytes / (prod_ms * 1e-3) / 1e9
+    # Algorithmic bytes of one product launch: X once, the factor once, the
+    # FP64 result once (C^T = X^T W_y: n rows; A = X H_w^T: m rows).
+    bytes_ct = m * n * sx + m * r * 4 + n * r * 8
+    bytes_a = m * n * sx + n * r * 4 + m * r * 8
+    prod_ms = 0.5 * (phases["prod_ct"] + phases["prod_a"])
+    achieved = (bytes_ct + bytes_a) / ((phases["prod_ct"] + phases["prod_a"]) * 1e-3) / 1e9
     iter_bytes = 2 * m * n * sx + 7 * (m + n) * r * 4
     key = f"planted_{m}x{n}_r{r}_{args.x_dtype}_{args.prod}"
     traffic = measured_traffic(key)
@@ -175,7 +195,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "X-streaming product",
-                     "bytes_per_launch": prod_bytes, "ms_per_launch": prod_ms},
+                     "bytes_per_launch": 0.5 * (bytes_ct + bytes_a), "ms_per_launch": prod_ms},
     }
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(args)

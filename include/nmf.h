@@ -153,13 +153,26 @@ nmf_status nmf_read(nmf_ctx *ctx, float *W, float *H, int32_t on_device,
                     double *trace, int32_t trace_cap, int32_t *n_iter,
                     uint8_t *accepted, double *beta, void *stream);
 
-/* Per-phase timing. Runs `iters` further outer iterations (they advance the
+/* Kernels of one outer iteration, in launch order (the phases timed by
+ * nmf_profile). The slicing phases run only with the exact-integer products
+ * (NMF_PROD_MFMA_EXACT); otherwise they take no time. */
+enum nmf_phase {
+    NMF_PHASE_SLICE_W = 0,   /* W_y into int8 slices (operand of X^T W_y) */
+    NMF_PHASE_PROD_CT = 1,   /* C^T = X^T W_y */
+    NMF_PHASE_SWEEP_H = 2,   /* H sweeps, extrapolation, partial Grams */
+    NMF_PHASE_FINISH_H = 3,  /* Gram of H_w, its inverse diagonal and column maxima */
+    NMF_PHASE_SLICE_H = 4,   /* H_w into int8 slices (operand of X H_w^T) */
+    NMF_PHASE_PROD_A = 5,    /* A = X H_w^T */
+    NMF_PHASE_SWEEP_W = 6,   /* W sweeps, extrapolation, partial Grams, <W_n, A> */
+    NMF_PHASE_FINISH_W = 7,  /* Grams of W_n and W_y', e(k), accept/restart, beta */
+    NMF_PHASE_COUNT = 8
+};
+
+/* Per-kernel timing. Runs `iters` further outer iterations (they advance the
  * solve like nmf_iterate, within max_iter) launched one kernel at a time on
- * `stream`, with a HIP event recorded before and after each phase, waits for
- * them, and writes the average duration in milliseconds of each phase to
- * ms[0..3]: ms[0] = X^T W_y (first product), ms[1] = H sweeps with their
- * epilogue, ms[2] = X H_w^T (second product), ms[3] = W sweeps with their
- * epilogue and the accept/restart decision.
+ * `stream`, with a HIP event recorded on `stream` before and after each
+ * kernel, waits for them, and writes the average duration in milliseconds of
+ * each phase to ms[0 .. NMF_PHASE_COUNT - 1] (enum nmf_phase).
  * Errors: NMF_E_STATE before nmf_start, NMF_E_INVAL (iters < 1, ms NULL, or
  * fewer than iters iterations left before max_iter), NMF_E_DEVICE. */
 nmf_status nmf_profile(nmf_ctx *ctx, int32_t iters, void *stream, double *ms);

@@ -50,6 +50,10 @@ class Prod(enum.IntEnum):
     MFMA_FAST = 3
 
 
+# Kernels of one outer iteration in launch order (enum nmf_phase).
+PHASES = ("slice_w", "prod_ct", "sweep_h", "finish_h", "slice_h", "prod_a", "sweep_w",
+          "finish_w")
+
 FLAG_BETABAR_LAST_ACCEPTED = 1
 FLAG_CMP_LAST_ACCEPTED = 2
 
@@ -243,11 +247,11 @@ class Solver:
         self._check(lib().nmf_iterate(self._ctx, int(iters), _stream(stream)))
 
     def profile(self, iters, stream=None):
-        """nmf_profile: average ms of the four phases over `iters` eager
-        iterations (products, H sweeps, W sweeps + decision)."""
-        ms = np.zeros(4)
+        """nmf_profile: average ms of each kernel of an outer iteration over
+        `iters` eager iterations, keyed by PHASES."""
+        ms = np.zeros(len(PHASES))
         self._check(lib().nmf_profile(self._ctx, int(iters), _stream(stream), _ptr(ms)))
-        return dict(prod_xt_w=ms[0], sweep_h=ms[1], prod_x_h=ms[2], sweep_w=ms[3])
+        return {name: float(v) for name, v in zip(PHASES, ms)}
 
     def read(self, W=None, H=None, stream=None) -> Result:
         """nmf_read into host arrays, or into given torch CUDA tensors."""

@@ -259,23 +259,25 @@ nmf_status upload_dense(nmf_ctx *c, const nmf_matrix *X)
     return NMF_OK;
 }
 
-// One outer iteration as four launches. With `ev` non-null, event ev[i] is
-// recorded before phase i and ev[4] after the last one.
+// One outer iteration (eight kernels; four launch steps). With `ev`
+// non-null, ev[i] is recorded before kernel i (enum nmf_phase) and
+// ev[NMF_PHASE_COUNT] after the last one.
 nmf_status enqueue_iteration(nmf_ctx *c, hipStream_t s, hipEvent_t *ev = nullptr)
 {
     const int rp = c->rp, xd = c->p.x_dtype, pk = c->prod_kernel;
     Buffers &b = c->b;
+    auto e = [&](int i) { return ev ? ev[i] : nullptr; };
     // a1: C^T = X^T W_y ; a2-a4: H sweeps + epilogue ; a5: A = X H_w^T ;
     // a6-a8: W sweeps + epilogue + decision.
-    if (ev) HIP_TRY(c, hipEventRecord(ev[0], s));
-    HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pc, s));
-    if (ev) HIP_TRY(c, hipEventRecord(ev[1], s));
-    HIP_TRY(c, nmf::launch_sweep_h(rp, c->n, c->r, c->p.inner_k, b, c->m, s));
-    if (ev) HIP_TRY(c, hipEventRecord(ev[2], s));
-    HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pa, s));
-    if (ev) HIP_TRY(c, hipEventRecord(ev[3], s));
-    HIP_TRY(c, nmf::launch_sweep_w(rp, c->m, c->r, c->p.inner_k, b, c->n, s));
-    if (ev) HIP_TRY(c, hipEventRecord(ev[4], s));
+    if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SLICE_W], s));
+    HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pc, s, e(NMF_PHASE_PROD_CT)));
+    if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SWEEP_H], s));
+    HIP_TRY(c, nmf::launch_sweep_h(rp, c->n, c->r, c->p.inner_k, b, s, e(NMF_PHASE_FINISH_H)));
+    if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SLICE_H], s));
+    HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pa, s, e(NMF_PHASE_PROD_A)));
+    if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SWEEP_W], s));
+    HIP_TRY(c, nmf::launch_sweep_w(rp, c->m, c->r, c->p.inner_k, b, s, e(NMF_PHASE_FINISH_W)));
+    if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_COUNT], s));
     return NMF_OK;
 }
 
@@ -524,26 +526,27 @@ nmf_status nmf_profile(nmf_ctx *c, int32_t iters, void *stream, double *ms)
                     c->p.max_iter - c->launched);
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));
-    std::vector<hipEvent_t> ev((size_t)iters * 5, nullptr);
+    constexpr int NE = NMF_PHASE_COUNT + 1;
+    std::vector<hipEvent_t> ev((size_t)iters * NE, nullptr);
     nmf_status st = NMF_OK;
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
             st = fail(c, NMF_E_DEVICE, "hipEventCreate failed");
             break;
         }
-    for (int32_t i = 0; st == NMF_OK && i < iters; ++i) st = enqueue_iteration(c, s, &ev[(size_t)i * 5]);
+    for (int32_t i = 0; st == NMF_OK && i < iters; ++i) st = enqueue_iteration(c, s, &ev[(size_t)i * NE]);
     if (st == NMF_OK) {
         c->launched += iters;
-        double acc[4] = {0, 0, 0, 0};
+        double acc[NMF_PHASE_COUNT] = {};
         hipError_t e = hipEventSynchronize(ev.back());
         for (int32_t i = 0; e == hipSuccess && i < iters; ++i)
-            for (int ph = 0; ph < 4 && e == hipSuccess; ++ph) {
+            for (int ph = 0; ph < NMF_PHASE_COUNT && e == hipSuccess; ++ph) {
                 float t = 0.f;
-                e = hipEventElapsedTime(&t, ev[(size_t)i * 5 + ph], ev[(size_t)i * 5 + ph + 1]);
+                e = hipEventElapsedTime(&t, ev[(size_t)i * NE + ph], ev[(size_t)i * NE + ph + 1]);
                 acc[ph] += t;
             }
         if (e != hipSuccess) st = fail(c, NMF_E_DEVICE, "event timing failed: %s", hipGetErrorString(e));
-        for (int ph = 0; ph < 4; ++ph) ms[ph] = acc[ph] / iters;
+        for (int ph = 0; ph < NMF_PHASE_COUNT; ++ph) ms[ph] = acc[ph] / iters;
     }
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);

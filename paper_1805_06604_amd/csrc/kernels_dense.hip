@@ -180,7 +180,7 @@ __global__ void sum_parts_kernel(const double *__restrict__ part, int nblk, doub
 }  // namespace
 
 namespace i8 {
-void launch(int rp, const ProdArgs &a, hipStream_t s);
+void launch(int rp, const ProdArgs &a, hipStream_t s, hipEvent_t mid);
 }
 namespace mfma {
 void launch_f32(int rp, int L, const ProdArgs &a, hipStream_t s);
@@ -188,9 +188,16 @@ void launch_bf16(int rp, int L, const ProdArgs &a, hipStream_t s);
 void launch_f16(int rp, int L, const ProdArgs &a, hipStream_t s);
 }  // namespace mfma
 
-hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hipStream_t s)
+hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hipStream_t s,
+                          hipEvent_t mid)
 {
     if (rp != 16 && rp != 32 && rp != 48 && rp != 64) return hipErrorInvalidValue;
+    if (kernel == PK_MFMA_I8) {
+        i8::launch(rp, a, s, mid);
+        return hipGetLastError();
+    }
+    // No slicing step: the "between" mark goes before the product.
+    if (mid) (void)hipEventRecord(mid, s);
     if (kernel == PK_VALU) {
         switch (xdtype) {
         case 0: return prod_fp64_dispatch<float>(rp, a, s);
@@ -198,10 +205,6 @@ hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hip
         case 2: return prod_fp64_dispatch<__half>(rp, a, s);
         default: return hipErrorInvalidValue;
         }
-    }
-    if (kernel == PK_MFMA_I8) {
-        i8::launch(rp, a, s);
-        return hipGetLastError();
     }
     const int L = (kernel == PK_MFMA_L2) ? 2 : 1;
     switch (xdtype) {

@@ -75,18 +75,16 @@ __global__ void unpack_kernel(int rp, int64_t m, int64_t n, int r,
     }
 
 hipError_t launch_sweep_h(int rp, int64_t n, int r, int inner_k, const Buffers &b,
-                          int64_t m, hipStream_t s)
+                          hipStream_t s, hipEvent_t mid)
 {
-    (void)m;
-    NMF_RP_CALL(rp, sweep_h, n, r, inner_k, b, s);
+    NMF_RP_CALL(rp, sweep_h, n, r, inner_k, b, s, mid);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_w(int rp, int64_t m, int r, int inner_k, const Buffers &b,
-                          int64_t n, hipStream_t s)
+                          hipStream_t s, hipEvent_t mid)
 {
-    (void)n;
-    NMF_RP_CALL(rp, sweep_w, m, r, inner_k, b, s);
+    NMF_RP_CALL(rp, sweep_w, m, r, inner_k, b, s, mid);
     return hipGetLastError();
 }
 

@@ -122,13 +122,16 @@ struct Buffers {
 enum Counter { CNT_H = 0, CNT_W = 64, CNT_G = 128, CNT_N = 192 };
 
 // ------------------------------------------------------------ launchers
-// All return hipGetLastError() after enqueueing on `s`.
-hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hipStream_t s);
+// All return hipGetLastError() after enqueueing on `s`. A non-null `mid` is
+// recorded on `s` between the two kernels of the step (after the factor
+// slicing of a product, after the sweep kernel of a half-iteration).
+hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hipStream_t s,
+                          hipEvent_t mid = nullptr);
 
 hipError_t launch_sweep_h(int rp, int64_t n, int r, int inner_k, const Buffers &b,
-                          int64_t m, hipStream_t s);
+                          hipStream_t s, hipEvent_t mid = nullptr);
 hipError_t launch_sweep_w(int rp, int64_t m, int r, int inner_k, const Buffers &b,
-                          int64_t n, hipStream_t s);
+                          hipStream_t s, hipEvent_t mid = nullptr);
 
 // Set-up of e(0): Gram of H0 (slot 0) into GH, then Gram of W0 (slot 0) into
 // GW[0] together with <W0, A>, and the initial error into the state.

@@ -245,9 +245,10 @@ __global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
 }
 
 template <int RP>
-void launch(const ProdArgs &a, hipStream_t s)
+void launch(const ProdArgs &a, hipStream_t s, hipEvent_t mid)
 {
     slice_factor_kernel<RP><<<(unsigned)(a.ld / kKT), 256, 0, s>>>(a);
+    if (mid) (void)hipEventRecord(mid, s);
     const int64_t blocks = (a.rows_pad / kBM) * a.nsplit;
     prod_i8_kernel<RP><<<(unsigned)blocks, kWaves * 64, 0, s>>>(a);
 }

@@ -48,13 +48,13 @@ __global__ __launch_bounds__(256) void slice_rows_kernel(const XT *__restrict__ 
 
 }  // namespace
 
-void launch(int rp, const ProdArgs &a, hipStream_t s)
+void launch(int rp, const ProdArgs &a, hipStream_t s, hipEvent_t mid)
 {
     switch (rp) {
-    case 16: launch<16>(a, s); break;
-    case 32: launch<32>(a, s); break;
-    case 48: launch<48>(a, s); break;
-    case 64: launch<64>(a, s); break;
+    case 16: launch<16>(a, s, mid); break;
+    case 32: launch<32>(a, s, mid); break;
+    case 48: launch<48>(a, s, mid); break;
+    case 64: launch<64>(a, s, mid); break;
     default: break;
     }
 }

@@ -487,7 +487,7 @@ template <int RP>
 struct Launch {
     template <int MODE>
     static void run(int64_t rows, int r, int K, const Buffers &b, bool w_side, uint32_t *counter,
-                    hipStream_t s)
+                    hipStream_t s, hipEvent_t mid = nullptr)
     {
         constexpr int NG = ModeInfo<MODE>::ngram;
         HalsArgs h{};
@@ -513,6 +513,7 @@ struct Launch {
         h.st = b.st;
         const int nblk = (int)((rows + kRows - 1) / kRows);
         hals_kernel<RP, MODE><<<nblk, kThreads, 0, s>>>(h);
+        if (mid) (void)hipEventRecord(mid, s);
 
         FinArgs f{};
         f.part = b.part_g;
@@ -530,13 +531,13 @@ struct Launch {
         const int fblk = (rec_len<RP>(NG) + 15) / 16;
         finish_kernel<RP, MODE><<<fblk, 256, 0, s>>>(f);
     }
-    static void sweep_h(int64_t n, int r, int K, const Buffers &b, hipStream_t s)
+    static void sweep_h(int64_t n, int r, int K, const Buffers &b, hipStream_t s, hipEvent_t mid)
     {
-        run<SWEEP_H>(n, r, K, b, false, b.counters + CNT_H, s);
+        run<SWEEP_H>(n, r, K, b, false, b.counters + CNT_H, s, mid);
     }
-    static void sweep_w(int64_t m, int r, int K, const Buffers &b, hipStream_t s)
+    static void sweep_w(int64_t m, int r, int K, const Buffers &b, hipStream_t s, hipEvent_t mid)
     {
-        run<SWEEP_W>(m, r, K, b, true, b.counters + CNT_W, s);
+        run<SWEEP_W>(m, r, K, b, true, b.counters + CNT_W, s, mid);
     }
     static void setup_h(int64_t n, int r, const Buffers &b, hipStream_t s)
     {

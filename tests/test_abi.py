@@ -23,6 +23,14 @@ def test_header_and_binding_agree():
     assert sorted(P.EXPORTS) == names
 
 
+def test_phase_names_follow_the_header_enum():
+    text = open(os.path.join(ROOT, "include", "nmf.h")).read()
+    found = re.findall(r"NMF_PHASE_([A-Z_]+) = (\d+)", text)
+    names = [n.lower() for n, v in sorted(found, key=lambda t: int(t[1])) if n != "COUNT"]
+    count = dict(found)["COUNT"]
+    assert tuple(names) == P.PHASES and int(count) == len(P.PHASES)
+
+
 def test_library_exports_every_declared_symbol():
     lib = P.lib()
     for name in declared_functions():
