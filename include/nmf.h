@@ -114,9 +114,16 @@ void nmf_params_default(nmf_params *p);
 /* Validates X and p, uploads X (and the transposed copy the second product
  * streams), converts it to x_dtype and computes ||X||_F^2 in FP64 from the
  * given FP32 values. X may be freed once this returns.
+ * Sparse X (NMF_CSR): the CSR arrays are copied, the CSC copy (the CSR form
+ * of X^T) is built on the host, and both products run as sparse products
+ * whose FP32 x FP32 terms are exact in FP64 and summed in FP64 in a fixed
+ * order (rows are split into work items of bounded nonzeros, so a long row
+ * costs like many short ones). Sparse X needs x_dtype = NMF_X_F32 and a
+ * prod other than NMF_PROD_MFMA_FAST (NMF_E_UNSUPPORTED otherwise); prod is
+ * otherwise ignored.
  * Errors: NMF_E_INVAL (shape, malformed CSR, non-finite X, all-zero X, any
- * parameter out of domain), NMF_E_UNSUPPORTED (r > 64), NMF_E_NOMEM,
- * NMF_E_DEVICE. On error *out is NULL. */
+ * parameter out of domain), NMF_E_UNSUPPORTED (r > 64; the sparse limits
+ * above), NMF_E_NOMEM, NMF_E_DEVICE. On error *out is NULL. */
 nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out);
 
 /* Synchronous solve (Algorithm 2, first step through max_iter iterations).

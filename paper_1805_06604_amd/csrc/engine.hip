@@ -29,6 +29,9 @@ struct nmf_ctx {
     int prod_kernel = nmf::PK_MFMA_L2;
     nmf::ProdArgs pa{};  // A = X H_w^T
     nmf::ProdArgs pc{};  // C^T = X^T W_y
+    nmf::CsrPlan csr_x{};    // sparse X: CSR of X (for A) and of X^T (for C^T)
+    nmf::CsrPlan csr_xt{};
+    std::vector<void *> extra;   // device arrays of the sparse plans
     double nx2 = 0.0;
     Buffers b;
     hipStream_t own = nullptr;
@@ -69,8 +72,9 @@ int round_rank(int r) { return ((r + 15) / 16) * 16; }
 
 int64_t round_up(int64_t v, int64_t q) { return ((v + q - 1) / q) * q; }
 
-int choose_kernel(const nmf_params *p)
+int choose_kernel(const nmf_params *p, int fmt)
 {
+    if (fmt == NMF_CSR) return nmf::PK_CSR;
     switch (p->prod) {
     case NMF_PROD_VALU: return nmf::PK_VALU;
     case NMF_PROD_MFMA_EXACT: return nmf::PK_MFMA_I8;
@@ -89,7 +93,7 @@ void plan_product(nmf::ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, 
     a.rows_pad = rows_pad;
     a.K = K;
     a.ld = ld;
-    if (kernel == nmf::PK_VALU) {
+    if (kernel == nmf::PK_VALU || kernel == nmf::PK_CSR) {
         a.nsplit = 1;
         a.kchunk = ld;
         return;
@@ -150,8 +154,30 @@ nmf_status check_matrix(const nmf_matrix *X)
                 return fail(nullptr, NMF_E_INVAL, "X has a non-finite entry at %lld", (long long)i);
         return NMF_OK;
     }
-    if (X->fmt == NMF_CSR)
-        return fail(nullptr, NMF_E_UNSUPPORTED, "CSR input is not provided by this build");
+    if (X->fmt == NMF_CSR) {
+        if (X->nnz < 0) return fail(nullptr, NMF_E_INVAL, "nnz = %lld < 0", (long long)X->nnz);
+        if (!X->row_ptr || (X->nnz > 0 && (!X->col_idx || !X->val)))
+            return fail(nullptr, NMF_E_INVAL, "CSR X has a NULL array");
+        if (X->nnz >= ((int64_t)1 << 40))
+            return fail(nullptr, NMF_E_UNSUPPORTED, "nnz above 2^40 is not provided");
+        if (X->row_ptr[0] != 0 || X->row_ptr[X->m] != X->nnz)
+            return fail(nullptr, NMF_E_INVAL, "CSR row_ptr must start at 0 and end at nnz");
+        for (int64_t i = 0; i < X->m; ++i) {
+            const int64_t b = X->row_ptr[i], e = X->row_ptr[i + 1];
+            if (e < b) return fail(nullptr, NMF_E_INVAL, "CSR row_ptr decreases at row %lld", (long long)i);
+            for (int64_t j = b; j < e; ++j) {
+                const int32_t c = X->col_idx[j];
+                if (c < 0 || c >= X->n)
+                    return fail(nullptr, NMF_E_INVAL, "CSR column %d out of range at %lld", c, (long long)j);
+                if (j > b && c <= X->col_idx[j - 1])
+                    return fail(nullptr, NMF_E_INVAL,
+                                "CSR columns must increase strictly within a row (row %lld)", (long long)i);
+                if (!std::isfinite(X->val[j]))
+                    return fail(nullptr, NMF_E_INVAL, "X has a non-finite entry at %lld", (long long)j);
+            }
+        }
+        return NMF_OK;
+    }
     return fail(nullptr, NMF_E_INVAL, "fmt = %d unknown", X->fmt);
 }
 
@@ -159,6 +185,8 @@ void free_all(nmf_ctx *c)
 {
     if (c->exec) (void)hipGraphExecDestroy(c->exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (void *p : c->extra)
+        if (p) (void)hipFree(p);
     void *ptrs[] = {c->X, c->Xt, c->zexp_x, c->zexp_xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH,
                     c->b.A, c->b.Ct, c->b.part_g, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
                     c->b.accepted, c->b.beta_used, c->b.stage, c->b.fsl, c->b.texp};
@@ -187,6 +215,9 @@ nmf_status alloc_buffers(nmf_ctx *c)
     HIP_TRY(c, dalloc(&b.GH, (size_t)gs));
     HIP_TRY(c, dalloc(&b.A, (size_t)c->pa.nsplit * b.m_pad * rp));
     HIP_TRY(c, dalloc(&b.Ct, (size_t)c->pc.nsplit * b.n_pad * rp));
+    // Rows that no product writes (padding; empty rows of a sparse X) read as 0.
+    HIP_TRY(c, hipMemset(b.A, 0, sizeof(double) * c->pa.nsplit * b.m_pad * rp));
+    HIP_TRY(c, hipMemset(b.Ct, 0, sizeof(double) * c->pc.nsplit * b.n_pad * rp));
     c->pa.Y = b.A;
     c->pc.Y = b.Ct;
     HIP_TRY(c, dalloc(&b.part_g, (size_t)(nblk * rec)));
@@ -259,6 +290,94 @@ nmf_status upload_dense(nmf_ctx *c, const nmf_matrix *X)
     return NMF_OK;
 }
 
+// Copies a host array to a new device array owned by the context.
+template <typename T>
+hipError_t to_device(nmf_ctx *c, const T *h, size_t count, const T **out)
+{
+    T *d = nullptr;
+    hipError_t e = dalloc(&d, count);
+    if (e != hipSuccess) return e;
+    c->extra.push_back(d);
+    if (count) e = hipMemcpy(d, h, sizeof(T) * count, hipMemcpyHostToDevice);
+    *out = d;
+    return e;
+}
+
+// Work items of a sparse product (see CsrPlan) and their device copies.
+hipError_t build_plan(nmf_ctx *c, int64_t rows, const int64_t *rp, const int32_t *col,
+                      const float *val, nmf::CsrPlan *P)
+{
+    const int64_t T = nmf::csr_item_nnz(c->rp);
+    std::vector<int32_t> irow, islot, lrow, lfirst, lcount;
+    std::vector<int64_t> ibeg, iend;
+    int32_t slots = 0;
+    for (int64_t i = 0; i < rows; ++i) {
+        const int64_t b = rp[i], e = rp[i + 1];
+        if (e == b) continue;
+        const int64_t parts = (e - b + T - 1) / T;
+        if (parts > 1) {
+            lrow.push_back((int32_t)i);
+            lfirst.push_back(slots);
+            lcount.push_back((int32_t)parts);
+        }
+        for (int64_t q = 0; q < parts; ++q) {
+            irow.push_back((int32_t)i);
+            ibeg.push_back(b + q * T);
+            iend.push_back(std::min(e, b + (q + 1) * T));
+            islot.push_back(parts > 1 ? slots++ : -1);
+        }
+    }
+    const int64_t nnz = rp[rows];
+    P->rows = rows;
+    P->nitems = (int64_t)irow.size();
+    P->nlong = (int64_t)lrow.size();
+    hipError_t e = to_device(c, rp, (size_t)rows + 1, &P->row_ptr);
+    if (e == hipSuccess) e = to_device(c, col, (size_t)nnz, &P->col);
+    if (e == hipSuccess) e = to_device(c, val, (size_t)nnz, &P->val);
+    if (e == hipSuccess) e = to_device(c, irow.data(), irow.size(), &P->item_row);
+    if (e == hipSuccess) e = to_device(c, ibeg.data(), ibeg.size(), &P->item_beg);
+    if (e == hipSuccess) e = to_device(c, iend.data(), iend.size(), &P->item_end);
+    if (e == hipSuccess) e = to_device(c, islot.data(), islot.size(), &P->item_slot);
+    if (e == hipSuccess) e = to_device(c, lrow.data(), lrow.size(), &P->long_row);
+    if (e == hipSuccess) e = to_device(c, lfirst.data(), lfirst.size(), &P->long_first);
+    if (e == hipSuccess) e = to_device(c, lcount.data(), lcount.size(), &P->long_count);
+    if (e == hipSuccess) {
+        double *part = nullptr;
+        e = dalloc(&part, (size_t)std::max<int32_t>(slots, 1) * c->rp);
+        if (e == hipSuccess) c->extra.push_back(part);
+        P->partial = part;
+    }
+    return e;
+}
+
+// Sparse X: the CSR as given, its transpose (CSC of X, columns in row order)
+// built here, the work items of both products, and ||X||^2 from the values.
+nmf_status upload_csr(nmf_ctx *c, const nmf_matrix *X)
+{
+    const int64_t m = c->m, n = c->n, nnz = X->nnz;
+    std::vector<int64_t> cp((size_t)n + 1, 0);
+    for (int64_t j = 0; j < nnz; ++j) ++cp[(size_t)X->col_idx[j] + 1];
+    for (int64_t k = 0; k < n; ++k) cp[k + 1] += cp[k];
+    std::vector<int64_t> next(cp.begin(), cp.end() - 1);
+    std::vector<int32_t> ri((size_t)nnz);
+    std::vector<float> rv((size_t)nnz);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = X->row_ptr[i]; j < X->row_ptr[i + 1]; ++j) {
+            const int64_t pos = next[X->col_idx[j]]++;
+            ri[pos] = (int32_t)i;
+            rv[pos] = X->val[j];
+        }
+    HIP_TRY(c, build_plan(c, m, X->row_ptr, X->col_idx, X->val, &c->csr_x));
+    HIP_TRY(c, build_plan(c, n, cp.data(), ri.data(), rv.data(), &c->csr_xt));
+    double *nx2 = nullptr;
+    HIP_TRY(c, dalloc(&nx2, 1));
+    c->extra.push_back(nx2);
+    HIP_TRY(c, nmf::launch_sumsq(c->csr_x.val, nnz, c->b.part_d, 1024, nx2, c->own));
+    HIP_TRY(c, hipStreamSynchronize(c->own));
+    HIP_TRY(c, hipMemcpy(&c->nx2, nx2, sizeof(double), hipMemcpyDeviceToHost));
+    return NMF_OK;
+}
+
 // One outer iteration (eight kernels; four launch steps). With `ev`
 // non-null, ev[i] is recorded before kernel i (enum nmf_phase) and
 // ev[NMF_PHASE_COUNT] after the last one.
@@ -328,6 +447,9 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
     if (st != NMF_OK) return st;
     st = check_matrix(X);
     if (st != NMF_OK) return st;
+    if (X->fmt == NMF_CSR && (p->x_dtype != NMF_X_F32 || p->prod == NMF_PROD_MFMA_FAST))
+        return fail(nullptr, NMF_E_UNSUPPORTED,
+                    "sparse X is kept in FP32 with FP64 sums: x_dtype must be F32 and prod not MFMA_FAST");
 
     nmf_ctx *c = new (std::nothrow) nmf_ctx();
     if (!c) return fail(nullptr, NMF_E_NOMEM, "host allocation failed");
@@ -337,7 +459,7 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
     c->r = p->r;
     c->rp = round_rank(p->r);
     c->fmt = X->fmt;
-    c->prod_kernel = choose_kernel(p);
+    c->prod_kernel = choose_kernel(p, X->fmt);
     c->b.m_pad = round_up(c->m, 128);
     c->b.n_pad = round_up(c->n, 128);
     c->ldx = round_up(c->n, 64);
@@ -355,7 +477,7 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
         return NMF_E_DEVICE;
     }
     st = alloc_buffers(c);
-    if (st == NMF_OK) st = upload_dense(c, X);
+    if (st == NMF_OK) st = (X->fmt == NMF_CSR) ? upload_csr(c, X) : upload_dense(c, X);
     if (st == NMF_OK) {
         // A = X H_w^T reads X and the H slots; C^T = X^T W_y reads X^T and the W slots.
         c->pa.Z = c->X;
@@ -378,6 +500,8 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
         c->pc.gram_slot_stride = nmf::gram_stride(c->rp);
         c->pc.Fsl = c->b.fsl;
         c->pc.texp = c->b.texp;
+        c->pa.csr = &c->csr_x;
+        c->pc.csr = &c->csr_xt;
     }
     if (st == NMF_OK && !(c->nx2 > 0.0))
         st = fail(c, NMF_E_INVAL, "X is zero: the relative error is undefined");

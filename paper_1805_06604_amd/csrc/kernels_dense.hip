@@ -182,6 +182,9 @@ __global__ void sum_parts_kernel(const double *__restrict__ part, int nblk, doub
 namespace i8 {
 void launch(int rp, const ProdArgs &a, hipStream_t s, hipEvent_t mid);
 }
+namespace csr {
+hipError_t launch(int rp, const ProdArgs &a, hipStream_t s);
+}
 namespace mfma {
 void launch_f32(int rp, int L, const ProdArgs &a, hipStream_t s);
 void launch_bf16(int rp, int L, const ProdArgs &a, hipStream_t s);
@@ -198,6 +201,7 @@ hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hip
     }
     // No slicing step: the "between" mark goes before the product.
     if (mid) (void)hipEventRecord(mid, s);
+    if (kernel == PK_CSR) return csr::launch(rp, a, s);
     if (kernel == PK_VALU) {
         switch (xdtype) {
         case 0: return prod_fp64_dispatch<float>(rp, a, s);

@@ -61,6 +61,32 @@ __host__ __device__ inline void plan_slots(int acc, int y, int32_t *n, int32_t *
     }
 }
 
+// A sparse operand (X, or X^T built from it) in CSR form on the device, with
+// the work split of its product: rows cut into items of at most a fixed
+// number of nonzeros. An item of a row that has a single item writes the
+// result row; the items of a longer row write partial rows into `partial`
+// (slots item_slot), which a second kernel sums in slot order.
+struct CsrPlan {
+    int64_t rows = 0;
+    const int64_t *row_ptr = nullptr;
+    const int32_t *col = nullptr;
+    const float *val = nullptr;
+    int64_t nitems = 0;
+    const int32_t *item_row = nullptr;
+    const int64_t *item_beg = nullptr;
+    const int64_t *item_end = nullptr;
+    const int32_t *item_slot = nullptr;   // -1: the item is its row
+    int64_t nlong = 0;
+    const int32_t *long_row = nullptr;
+    const int32_t *long_first = nullptr;
+    const int32_t *long_count = nullptr;
+    double *partial = nullptr;            // slots x RP
+};
+
+// Nonzeros per item of a sparse product at padded rank rp: 32 steps of the
+// wave, which takes 64 / (rp / 4) nonzeros per step.
+__host__ __device__ constexpr int64_t csr_item_nnz(int rp) { return 32 * (64 / (rp / 4)); }
+
 // One X-streaming product Y = Z F (see the product kernels). Z is X or the
 // resident X^T with rows padded to a multiple of 128 and rows of length ld (a
 // multiple of 64), zero-filled; Y holds nsplit partial sums over K-chunks.
@@ -84,13 +110,15 @@ struct ProdArgs {
     int64_t gram_slot_stride;
     signed char *Fsl;       // the factor in int8 slices: (ld / 64) x 4 x RP x 64
     int *texp;              // its column scale exponents (RP)
+    // Sparse kernel only: the CSR operand (host pointer to its plan).
+    const CsrPlan *csr;
 };
 
 // Product kernels: VALU FP64 FMA over FP32 operands (products exact, sums in
 // FP64), or matrix cores with operands split into BF16 parts keeping the part
 // pairs of relative weight >= 2^-8 (L = 1) or >= 2^-16 (L = 2), summed in
 // FP32 within a K-chunk.
-enum ProdKernel { PK_VALU = 0, PK_MFMA_L1 = 1, PK_MFMA_L2 = 2, PK_MFMA_I8 = 3 };
+enum ProdKernel { PK_VALU = 0, PK_MFMA_L1 = 1, PK_MFMA_L2 = 2, PK_MFMA_I8 = 3, PK_CSR = 4 };
 
 // Device buffers of one context. Factors are FP32, row-major with RP columns
 // (r rounded up to a multiple of 16; the padding stays zero):

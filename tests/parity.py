@@ -40,10 +40,14 @@ def oracle_run(p, max_iter, replay=None, flags=0, **kw):
                         flags=flags, **kw)
 
 
-def compare_to_oracle(p, gpu, max_iter, trace_iters=50, **kw):
+def compare_to_oracle(p, gpu, max_iter, trace_iters=50, oracle_flags=0, **kw):
     """Checks the GPU result `gpu` (binding.Result) against the oracle run
-    with the same parameters; returns a dict of the measured quantities."""
-    ref = oracle_run(p, max_iter, **kw)
+    with the same parameters; returns a dict of the measured quantities.
+    `oracle_flags` (e.g. oracle.ERR_REMARK1 on large sparse cases, where the
+    explicit residual would cost O(mnr)) applies to every oracle run."""
+    kw = dict(kw)
+    base = oracle_flags
+    ref = oracle_run(p, max_iter, flags=base, **kw)
     flips = 0
     if not np.array_equal(ref["accepted"], gpu.accepted[:ref["n_iter"]]):
         k = int(np.argmax(ref["accepted"] != gpu.accepted[:ref["n_iter"]]))
@@ -51,8 +55,8 @@ def compare_to_oracle(p, gpu, max_iter, trace_iters=50, **kw):
         assert margin < FLIP_MARGIN, (
             f"decision differs at iteration {k + 1} with margin {margin:.3e}")
         flips = int(np.sum(ref["accepted"] != gpu.accepted[:ref["n_iter"]]))
-        ref = oracle_run(p, max_iter, replay=gpu.accepted, **kw)
-    f32 = oracle_run(p, max_iter, replay=ref["accepted"], flags=oracle.ROUND_F32, **kw)
+        ref = oracle_run(p, max_iter, replay=gpu.accepted, flags=base, **kw)
+    f32 = oracle_run(p, max_iter, replay=ref["accepted"], flags=base | oracle.ROUND_F32, **kw)
     assert gpu.n_iter == ref["n_iter"]
     k = min(trace_iters, gpu.n_iter) + 1
     ro, rg, rf32 = ref["trace"][:k], gpu.trace[:k], f32["trace"][:k]

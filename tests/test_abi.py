@@ -84,3 +84,34 @@ def test_empty_matrix_rejected():
     with pytest.raises(P.NMFError) as e:
         P.Solver(np.ones((0, 3), np.float32), 1)
     assert e.value.status == P.Status.E_INVAL
+
+
+class _Csr:
+    def __init__(self, m, n, row_ptr, col_idx, val):
+        self.m, self.n = m, n
+        self.row_ptr = np.asarray(row_ptr, np.int64)
+        self.col_idx = np.asarray(col_idx, np.int32)
+        self.val = np.asarray(val, np.float32)
+
+
+@pytest.mark.parametrize("rp,ci,va,what", [
+    ([1, 2, 3], [0, 1], [1.0, 1.0], "start at 0"),             # row_ptr[0] != 0
+    ([0, 2, 1], [0, 1], [1.0, 1.0], "decreases"),              # row_ptr not monotone
+    ([0, 2, 2], [0, 5], [1.0, 1.0], "out of range"),           # column >= n
+    ([0, 2, 2], [1, 1], [1.0, 1.0], "strictly"),               # duplicate column
+    ([0, 2, 2], [2, 1], [1.0, 1.0], "strictly"),               # unsorted
+    ([0, 1, 2], [0, 1], [1.0, np.inf], "non-finite"),
+])
+def test_malformed_csr_rejected(rp, ci, va, what):
+    with pytest.raises(P.NMFError) as e:
+        P.Solver(_Csr(2, 3, rp, ci, va), 1)
+    assert e.value.status == P.Status.E_INVAL
+    assert what in str(e.value)
+
+
+def test_csr_needs_fp32_storage():
+    X = _Csr(2, 3, [0, 1, 2], [0, 2], [1.0, 2.0])
+    for kw in (dict(x_dtype=P.XDtype.BF16), dict(prod=P.Prod.MFMA_FAST)):
+        with pytest.raises(P.NMFError) as e:
+            P.Solver(X, 1, **kw)
+        assert e.value.status == P.Status.E_UNSUPPORTED
