@@ -37,8 +37,10 @@ typedef enum {
     NMF_E_NOMEM = 3,        /* host or device allocation failed              */
     NMF_E_DEVICE = 4,       /* a HIP call failed                             */
     NMF_E_NUMERIC = 5,      /* the initial error e(0) is not finite          */
-    NMF_E_STATE = 6         /* call out of order (e.g. nmf_iterate before
+    NMF_E_STATE = 6,        /* call out of order (e.g. nmf_iterate before
                                nmf_start)                                    */
+    NMF_PENDING = 7         /* not an error: the batched problem has not
+                               finished yet                                  */
 } nmf_status;
 
 typedef enum { NMF_DENSE_ROWMAJOR = 0, NMF_CSR = 1 } nmf_format;
@@ -183,6 +185,61 @@ enum nmf_phase {
  * Errors: NMF_E_STATE before nmf_start, NMF_E_INVAL (iters < 1, ms NULL, or
  * fewer than iters iterations left before max_iter), NMF_E_DEVICE. */
 nmf_status nmf_profile(nmf_ctx *ctx, int32_t iters, void *stream, double *ms);
+
+/* ------------------------------------------------------------------------
+ * Batched solves (serving many independent small problems on one GPU).
+ *
+ * A batch holds a fixed device-memory arena (hbm_budget bytes, allocated at
+ * nmf_batch_create) and runs continuous batching: every problem admitted
+ * into the arena advances by one outer iteration of Algorithm 2 per batch
+ * iteration, all problems of one padded rank sharing each kernel launch
+ * (grouped launches); problems join when they fit the arena and leave when
+ * they stop (max_iter or the tol rule), between batch iterations. Each
+ * problem follows exactly the single-problem algorithm with the exact-integer
+ * products (dense FP32 X only).
+ * ------------------------------------------------------------------------ */
+typedef struct nmf_batch nmf_batch;
+
+typedef struct {
+    int64_t hbm_budget;     /* bytes of device memory for the problems, > 0    */
+    int32_t max_active;     /* problems advanced together, 1..4096             */
+    int32_t check_every;    /* batch iterations between completion checks, >= 1 */
+} nmf_batch_params;
+
+/* Errors: NMF_E_INVAL (parameters), NMF_E_NOMEM (the arena), NMF_E_DEVICE.
+ * Messages of batch calls: nmf_last_error(NULL). */
+nmf_status nmf_batch_create(const nmf_batch_params *bp, nmf_batch **out);
+
+/* Queues one problem: dense FP32 X (m x n), parameters (x_dtype F32; prod is
+ * taken as NMF_PROD_MFMA_EXACT), W0 (m*r), H0 (r*n) host arrays, validated
+ * as for nmf_create / nmf_solve and copied (the caller may free them on
+ * return). *ticket identifies the problem. Nothing runs on the device until
+ * nmf_batch_step. Errors: as nmf_create, plus NMF_E_NOMEM if the problem
+ * alone exceeds the arena, NMF_E_UNSUPPORTED for CSR X or 16-bit storage. */
+nmf_status nmf_batch_submit(nmf_batch *b, const nmf_matrix *X, const nmf_params *p,
+                            const float *W0, const float *H0, int64_t *ticket);
+
+/* Admits queued problems in submission order while the arena and max_active
+ * allow, runs `iters` batch iterations (check_every at a time, retiring the
+ * problems that stopped after each check; a retired problem's result is kept
+ * on the host), and returns the numbers of active, queued and retired-unread
+ * problems (each pointer nullable). Blocks until the device work is done.
+ * Errors: NMF_E_INVAL (iters < 1), NMF_E_DEVICE. */
+nmf_status nmf_batch_step(nmf_batch *b, int32_t iters, int32_t *active, int32_t *queued,
+                          int32_t *retired);
+
+/* Result of a retired problem into host arrays (each nullable): W (m*r),
+ * H (r*n), trace[0..*n_iter] (trace_cap >= *n_iter + 1), and for
+ * k = 1..*n_iter the decision (1 accept, 0 restart) and the beta of
+ * iteration k; then the problem is forgotten. NMF_PENDING while the problem
+ * is queued or active; NMF_E_INVAL for an unknown ticket or a small
+ * trace_cap. */
+nmf_status nmf_batch_result(nmf_batch *b, int64_t ticket, float *W, float *H, double *trace,
+                            int32_t trace_cap, int32_t *n_iter, uint8_t *accepted,
+                            double *beta);
+
+/* Frees the arena and every pending problem. NULL is allowed. */
+void nmf_batch_destroy(nmf_batch *b);
 
 /* Frees every host and device resource of ctx. NULL is allowed. */
 void nmf_destroy(nmf_ctx *ctx);

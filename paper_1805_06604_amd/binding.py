@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libnmf.so")
 
 EXPORTS = ("nmf_params_default", "nmf_create", "nmf_solve", "nmf_start",
            "nmf_iterate", "nmf_read", "nmf_profile", "nmf_destroy",
-           "nmf_last_error")
+           "nmf_last_error", "nmf_batch_create", "nmf_batch_submit", "nmf_batch_step",
+           "nmf_batch_result", "nmf_batch_destroy")
 
 
 class Status(enum.IntEnum):
@@ -30,6 +31,7 @@ class Status(enum.IntEnum):
     E_DEVICE = 4
     E_NUMERIC = 5
     E_STATE = 6
+    PENDING = 7
 
 
 class Format(enum.IntEnum):
@@ -117,6 +119,16 @@ def lib():
         L.nmf_destroy.restype = None
         L.nmf_last_error.argtypes = [p]
         L.nmf_last_error.restype = C.c_char_p
+        L.nmf_batch_create.argtypes = [p, p]
+        L.nmf_batch_create.restype = i32
+        L.nmf_batch_submit.argtypes = [p, p, p, p, p, p]
+        L.nmf_batch_submit.restype = i32
+        L.nmf_batch_step.argtypes = [p, i32, p, p, p]
+        L.nmf_batch_step.restype = i32
+        L.nmf_batch_result.argtypes = [p, C.c_int64, p, p, p, i32, p, p, p]
+        L.nmf_batch_result.restype = i32
+        L.nmf_batch_destroy.argtypes = [p]
+        L.nmf_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -279,3 +291,85 @@ def solve(X, r, W0, H0, **params) -> Result:
     """One-shot solve: create a context, run nmf_solve, destroy it."""
     with Solver(X, r, **params) as s:
         return s.solve(W0, H0)
+
+
+class _BatchParams(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_active", C.c_int32),
+                ("check_every", C.c_int32)]
+
+
+class Batch:
+    """Batched solves (nmf_batch_*): many independent small dense problems
+    advanced together on the current GPU, inside a device arena of
+    ``hbm_budget`` bytes."""
+
+    def __init__(self, hbm_budget, max_active=256, check_every=10):
+        self._b = C.c_void_p()
+        bp = _BatchParams(int(hbm_budget), int(max_active), int(check_every))
+        st = lib().nmf_batch_create(C.byref(bp), C.byref(self._b))
+        if st != Status.OK:
+            raise NMFError(st, lib().nmf_last_error(None).decode())
+        self._shapes = {}
+
+    def _check(self, st):
+        if st != Status.OK:
+            raise NMFError(st, lib().nmf_last_error(None).decode())
+
+    def submit(self, X, r, W0, H0, **params):
+        """Queues one problem; returns its ticket."""
+        Xd = np.ascontiguousarray(X, dtype=np.float32)
+        W0 = np.ascontiguousarray(W0, dtype=np.float32)
+        H0 = np.ascontiguousarray(H0, dtype=np.float32)
+        m, n = Xd.shape
+        if W0.shape != (m, r) or H0.shape != (r, n):
+            raise ValueError("W0 must be (m, r) and H0 (r, n)")
+        mat = _Matrix()
+        mat.fmt, mat.m, mat.n = Format.DENSE, m, n
+        mat.dense = Xd.ctypes.data
+        prm = make_params(r, **params)
+        t = C.c_int64()
+        self._check(lib().nmf_batch_submit(self._b, C.byref(mat), C.byref(prm), _ptr(W0),
+                                           _ptr(H0), C.byref(t)))
+        self._shapes[t.value] = (m, n, r, prm.max_iter)
+        return t.value
+
+    def step(self, iters=1):
+        """Advances the batch; returns (active, queued, retired-unread)."""
+        a, q, d = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(lib().nmf_batch_step(self._b, int(iters), C.byref(a), C.byref(q), C.byref(d)))
+        return a.value, q.value, d.value
+
+    def result(self, ticket):
+        """The Result of a retired problem, or None while it is pending."""
+        m, n, r, max_iter = self._shapes[ticket]
+        W = np.empty((m, r), np.float32)
+        H = np.empty((r, n), np.float32)
+        trace = np.zeros(max_iter + 1)
+        acc = np.zeros(max(max_iter, 1), np.uint8)
+        beta = np.zeros(max(max_iter, 1))
+        nit = C.c_int32()
+        st = lib().nmf_batch_result(self._b, int(ticket), _ptr(W), _ptr(H), _ptr(trace),
+                                    max_iter + 1, C.byref(nit), _ptr(acc), _ptr(beta))
+        if st == Status.PENDING:
+            return None
+        self._check(st)
+        del self._shapes[ticket]
+        k = nit.value
+        return Result(W, H, trace[:k + 1], acc[:k].astype(bool), beta[:k], k)
+
+    def close(self):
+        if self._b:
+            lib().nmf_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

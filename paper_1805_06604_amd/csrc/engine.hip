@@ -87,7 +87,7 @@ int choose_kernel(const nmf_params *p, int fmt)
 // (about 512 for the kernels that run two per CU, 256 for the exact-integer
 // kernel, whose LDS ring takes a whole CU), K-chunks of whole 64-column tiles.
 void plan_product(nmf::ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, int64_t K,
-                  int64_t ld)
+                  int64_t ld, int64_t target_wg = 0)
 {
     a.rows = rows;
     a.rows_pad = rows_pad;
@@ -99,7 +99,7 @@ void plan_product(nmf::ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, 
         return;
     }
     const int64_t rb = rows_pad / 128, tiles = ld / 64;
-    const int64_t target = (kernel == nmf::PK_MFMA_I8) ? 256 : 512;
+    const int64_t target = target_wg > 0 ? target_wg : (kernel == nmf::PK_MFMA_I8) ? 256 : 512;
     int64_t want = (target + rb - 1) / rb;
     // The exact-integer sums stay below 2^31 for chunks of at most 65536.
     if (kernel == nmf::PK_MFMA_I8) want = std::max<int64_t>(want, (tiles + 1023) / 1024);
@@ -417,6 +417,21 @@ nmf_status build_graph(nmf_ctx *c)
 }
 
 }  // namespace
+
+namespace nmf {
+namespace host {
+void set_error(const std::string &msg) { g_err = msg; }
+nmf_status check_params(const nmf_params *p) { return ::check_params(p); }
+nmf_status check_matrix(const nmf_matrix *X) { return ::check_matrix(X); }
+int round_rank(int r) { return ::round_rank(r); }
+int64_t round_up(int64_t v, int64_t q) { return ::round_up(v, q); }
+void plan_product(ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, int64_t K, int64_t ld,
+                  int64_t target_wg)
+{
+    ::plan_product(a, kernel, rows, rows_pad, K, ld, target_wg);
+}
+}  // namespace host
+}  // namespace nmf
 
 extern "C" {
 

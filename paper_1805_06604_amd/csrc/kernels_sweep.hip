@@ -88,6 +88,13 @@ hipError_t launch_sweep_w(int rp, int64_t m, int r, int inner_k, const Buffers &
     return hipGetLastError();
 }
 
+hipError_t launch_group_sweep(int rp, bool w_side, const Group &gh, int hblocks, const Group &gf,
+                              int fblocks, hipStream_t s)
+{
+    NMF_RP_CALL(rp, group, w_side, gh, hblocks, gf, fblocks, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_setup_gram_h(int rp, int64_t n, int r, const Buffers &b, hipStream_t s)
 {
     NMF_RP_CALL(rp, setup_h, n, r, b, s);

@@ -149,6 +149,30 @@ struct Buffers {
 // Last-block counters, one per kernel kind, each on its own 256-byte line.
 enum Counter { CNT_H = 0, CNT_W = 64, CNT_G = 128, CNT_N = 192 };
 
+// A grouped launch runs one kernel over several problems at once: problem p
+// owns blocks prefix[p] .. prefix[p + 1] - 1 of the grid and reads its
+// argument record at base + p * stride (device memory).
+struct Group {
+    const char *base = nullptr;
+    int stride = 0;
+    const int *prefix = nullptr;
+    int np = 0;
+};
+
+// Problem of block b of a grouped launch, and the block's index within it.
+__device__ inline int group_find(const Group &g, int b, int *local, int *count)
+{
+    int lo = 0, hi = g.np;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (g.prefix[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    *local = b - g.prefix[lo];
+    *count = g.prefix[lo + 1] - g.prefix[lo];
+    return lo;
+}
+
 // ------------------------------------------------------------ launchers
 // All return hipGetLastError() after enqueueing on `s`. A non-null `mid` is
 // recorded on `s` between the two kernels of the step (after the factor
@@ -191,5 +215,15 @@ hipError_t launch_sumsq(const float *src, int64_t count, double *part, int nblk,
                         double *out, hipStream_t s);
 hipError_t launch_sumsq_typed(const void *v, int xdtype, int64_t count, double *part,
                               int nblk, double *out, hipStream_t s);
+
+// Grouped launches (one launch per kernel over several problems of one
+// padded rank): the exact-integer product (factor slicing, then product) and
+// a half-iteration of sweeps (sweep kernel, then finish kernel).
+namespace i8 {
+hipError_t launch_group(int rp, const Group &gs, int sblocks, const Group &gp, int pblocks,
+                        hipStream_t s);
+}
+hipError_t launch_group_sweep(int rp, bool w_side, const Group &gh, int hblocks, const Group &gf,
+                              int fblocks, hipStream_t s);
 
 }  // namespace nmf

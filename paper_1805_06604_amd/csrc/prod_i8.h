@@ -75,7 +75,7 @@ __host__ __device__ constexpr int fpart(int c, int part) { return part ^ ((c >> 
 // swizzled by fpart, zero past K), with column exponents t_k from the column
 // maxima; block 0 also stores t_k.
 template <int RP>
-__global__ __launch_bounds__(256) void slice_factor_kernel(ProdArgs a)
+__device__ __forceinline__ void slice_body(const ProdArgs &a, int bid)
 {
     __shared__ int s_texp[RP];
     const DevState *st = a.st;
@@ -90,10 +90,10 @@ __global__ __launch_bounds__(256) void slice_factor_kernel(ProdArgs a)
     const int tid = threadIdx.x;
     if (tid < RP) {
         s_texp[tid] = slice_exponent(colmax[tid]);
-        if (blockIdx.x == 0) a.texp[tid] = s_texp[tid];
+        if (bid == 0) a.texp[tid] = s_texp[tid];
     }
     __syncthreads();
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = bid;
     uint32_t *out = reinterpret_cast<uint32_t *>(a.Fsl + tile * (kSl * RP * kKT));
     for (int item = tid; item < RP * (kKT / 4); item += 256) {
         const int c = item % RP, kq = item / RP;
@@ -130,7 +130,7 @@ __device__ __forceinline__ void dma_wave(signed char *lds, const signed char *sr
 constexpr int kStages = 3;
 
 template <int RP>
-__global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
+__device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
 {
     constexpr int NCB = RP / 16;
     constexpr int FT = kSl * RP * kKT;                // factor tile bytes
@@ -146,8 +146,8 @@ __global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, lr = lane & 15;
-    const int kc = blockIdx.x % a.nsplit;
-    const int64_t rb = blockIdx.x / a.nsplit;
+    const int kc = bid % a.nsplit;
+    const int64_t rb = bid / a.nsplit;
     const int64_t kbeg = (int64_t)kc * a.kchunk;
     int64_t kend = kbeg + a.kchunk;
     if (kend > a.ld) kend = a.ld;
@@ -242,6 +242,46 @@ __global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
             }
         }
     }
+}
+
+template <int RP>
+__global__ __launch_bounds__(256) void slice_factor_kernel(ProdArgs a)
+{
+    slice_body<RP>(a, blockIdx.x);
+}
+
+template <int RP>
+__global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
+{
+    prod_body<RP>(a, blockIdx.x);
+}
+
+// Grouped forms (one launch over several problems of one padded rank).
+template <int RP>
+__global__ __launch_bounds__(256) void slice_factor_group_kernel(Group g)
+{
+    int lb, cnt;
+    const int p = group_find(g, blockIdx.x, &lb, &cnt);
+    slice_body<RP>(*reinterpret_cast<const ProdArgs *>(g.base + (size_t)p * g.stride), lb);
+}
+
+template <int RP>
+__global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_group_kernel(Group g)
+{
+    int lb, cnt;
+    const int p = group_find(g, blockIdx.x, &lb, &cnt);
+    prod_body<RP>(*reinterpret_cast<const ProdArgs *>(g.base + (size_t)p * g.stride), lb);
+}
+
+// Blocks of the two kernels of one product.
+inline int slice_blocks(const ProdArgs &a) { return (int)(a.ld / kKT); }
+inline int prod_blocks(const ProdArgs &a) { return (int)((a.rows_pad / kBM) * a.nsplit); }
+
+template <int RP>
+void launch_group(const Group &gs, int sblocks, const Group &gp, int pblocks, hipStream_t s)
+{
+    slice_factor_group_kernel<RP><<<sblocks, 256, 0, s>>>(gs);
+    prod_i8_group_kernel<RP><<<pblocks, kWaves * 64, 0, s>>>(gp);
 }
 
 template <int RP>

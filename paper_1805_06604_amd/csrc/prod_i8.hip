@@ -59,6 +59,19 @@ void launch(int rp, const ProdArgs &a, hipStream_t s, hipEvent_t mid)
     }
 }
 
+hipError_t launch_group(int rp, const Group &gs, int sblocks, const Group &gp, int pblocks,
+                        hipStream_t s)
+{
+    switch (rp) {
+    case 16: launch_group<16>(gs, sblocks, gp, pblocks, s); break;
+    case 32: launch_group<32>(gs, sblocks, gp, pblocks, s); break;
+    case 48: launch_group<48>(gs, sblocks, gp, pblocks, s); break;
+    case 64: launch_group<64>(gs, sblocks, gp, pblocks, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t slice_rows(const void *src, int xdtype, int64_t rows, int64_t cols, int64_t ld_src,
                       int64_t ld_dst, void *dst, int *zexp, hipStream_t s)
 {

@@ -92,14 +92,14 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 // of a grid run on all XCDs, whose L2 caches are not coherent with one
 // another, so the counter is updated at system scope (coherent at memory);
 // the fences write back and invalidate the L2 for the data.
-__device__ inline bool last_block(uint32_t *counter, int *s_flag)
+__device__ inline bool last_block(uint32_t *counter, int *s_flag, int nblk)
 {
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t prev =
             __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
-        *s_flag = (prev == gridDim.x - 1);
+        *s_flag = (prev == (uint32_t)nblk - 1);
     }
     __syncthreads();
     const bool last = *s_flag != 0;
@@ -180,7 +180,7 @@ struct HalsArgs {
 //   G = H_w H_w^T; W_y' = W_n + beta (W_n - W); <W_n, A>, Gram(W_n),
 //   Gram(W_y').
 template <int RP, int MODE>
-__global__ __launch_bounds__(kThreads, 1) void hals_kernel(HalsArgs a)
+__device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
 {
     using MI = ModeInfo<MODE>;
     constexpr int NB = RP / 16, NS = RP / 4, NG = MI::ngram;
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kThreads, 1) void hals_kernel(HalsArgs a)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, g = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * kRows + wave * 16;
+    const int64_t row0 = (int64_t)bid * kRows + wave * 16;
 
     DevState *st = a.st;
     int src = 0, dst_n = 0, dst_y = 0, acc_slot = 0, hp = 3;
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kThreads, 1) void hals_kernel(HalsArgs a)
         }
     }
 
-    double *rec = a.part + (size_t)blockIdx.x * LREC;
+    double *rec = a.part + (size_t)bid * LREC;
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi) {
         // Column maxima of the tile: over v, then over the 4 lane groups.
@@ -409,7 +409,7 @@ struct FinArgs {
 // inverse diagonal (0 beyond r or for a zero diagonal) and column maxima. The
 // last workgroup then forms e(k) and decides (W sides).
 template <int RP, int MODE>
-__global__ __launch_bounds__(256) void finish_kernel(FinArgs a)
+__device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
 {
     constexpr int NG = ModeInfo<MODE>::ngram;
     constexpr int GL = RP * RP + RP;
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(256) void finish_kernel(FinArgs a)
         slot[0] = 0;
     }
     const int o = threadIdx.x & 15, j = threadIdx.x >> 4;
-    const int e = blockIdx.x * 16 + o;
+    const int e = bid * 16 + o;
     const bool is_max = e < NG * GL && (e % GL) >= RP * RP;
     double v = 0.0;
     if (e < LREC) {
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void finish_kernel(FinArgs a)
             a.scratch[0] = s;
         }
     }
-    if (!last_block(a.counter, &s_last)) return;
+    if (!last_block(a.counter, &s_last, nblk)) return;
     if constexpr (ModeInfo<MODE>::s1) {
         const double *Gn = a.gram + slot[0] * a.gram_slot_stride;
         double s2 = 0.0;
@@ -482,6 +482,85 @@ __global__ __launch_bounds__(256) void finish_kernel(FinArgs a)
     if (threadIdx.x == 0) reset_counter(a.counter);
 }
 
+template <int RP, int MODE>
+__global__ __launch_bounds__(kThreads, 1) void hals_kernel(HalsArgs a)
+{
+    hals_body<RP, MODE>(a, blockIdx.x);
+}
+
+template <int RP, int MODE>
+__global__ __launch_bounds__(256) void finish_kernel(FinArgs a)
+{
+    finish_body<RP, MODE>(a, blockIdx.x, gridDim.x);
+}
+
+// Grouped forms: one launch over several problems of the same padded rank
+// (argument records and block ranges in g).
+template <int RP, int MODE>
+__global__ __launch_bounds__(kThreads, 1) void hals_group_kernel(Group g)
+{
+    int lb, cnt;
+    const int p = group_find(g, blockIdx.x, &lb, &cnt);
+    hals_body<RP, MODE>(*reinterpret_cast<const HalsArgs *>(g.base + (size_t)p * g.stride), lb);
+}
+
+template <int RP, int MODE>
+__global__ __launch_bounds__(256) void finish_group_kernel(Group g)
+{
+    int lb, cnt;
+    const int p = group_find(g, blockIdx.x, &lb, &cnt);
+    finish_body<RP, MODE>(*reinterpret_cast<const FinArgs *>(g.base + (size_t)p * g.stride), lb, cnt);
+}
+
+// Argument records of one half-iteration (or set-up step) of one problem.
+inline HalsArgs hals_args(int rp, int64_t rows, int r, int K, const Buffers &b, bool w_side)
+{
+    HalsArgs h{};
+    h.rows = rows;
+    h.r = r;
+    h.K = K;
+    h.fac = w_side ? b.Wf : b.Hf;
+    h.slot_stride = rows * rp;
+    if (w_side) {
+        h.lin = b.A;
+        h.nsplit = b.nsplit_a;
+        h.split_stride = b.m_pad * rp;
+        h.gram = b.GH;
+        h.gram_slot_stride = 0;
+    } else {
+        h.lin = b.Ct;
+        h.nsplit = b.nsplit_c;
+        h.split_stride = b.n_pad * rp;
+        h.gram = b.GW;
+        h.gram_slot_stride = gram_stride(rp);
+    }
+    h.part = b.part_g;
+    h.st = b.st;
+    return h;
+}
+
+inline FinArgs fin_args(int rp, int64_t rows, int r, const Buffers &b, bool w_side, uint32_t *counter)
+{
+    FinArgs f{};
+    f.part = b.part_g;
+    f.nblk = (int)((rows + kRows - 1) / kRows);
+    f.r = r;
+    f.gram = w_side ? b.GW : b.GH;
+    f.gram_slot_stride = w_side ? gram_stride(rp) : 0;
+    f.GH = b.GH;
+    f.scratch = b.part_d;
+    f.counter = counter;
+    f.st = b.st;
+    f.trace = b.trace;
+    f.accepted = b.accepted;
+    f.beta_used = b.beta_used;
+    return f;
+}
+
+// Blocks of the two kernels of a half-iteration.
+inline int hals_blocks(int64_t rows) { return (int)((rows + kRows - 1) / kRows); }
+inline int fin_blocks(int rp, int ngram) { return (int)((ngram * (rp * rp + rp) + 1 + 15) / 16); }
+
 // Enqueues one half-iteration (or a set-up step) of one padded rank.
 template <int RP>
 struct Launch {
@@ -490,46 +569,24 @@ struct Launch {
                     hipStream_t s, hipEvent_t mid = nullptr)
     {
         constexpr int NG = ModeInfo<MODE>::ngram;
-        HalsArgs h{};
-        h.rows = rows;
-        h.r = r;
-        h.K = K;
-        h.fac = w_side ? b.Wf : b.Hf;
-        h.slot_stride = rows * RP;
-        if (w_side) {
-            h.lin = b.A;
-            h.nsplit = b.nsplit_a;
-            h.split_stride = b.m_pad * RP;
-            h.gram = b.GH;
-            h.gram_slot_stride = 0;
-        } else {
-            h.lin = b.Ct;
-            h.nsplit = b.nsplit_c;
-            h.split_stride = b.n_pad * RP;
-            h.gram = b.GW;
-            h.gram_slot_stride = gram_stride(RP);
-        }
-        h.part = b.part_g;
-        h.st = b.st;
-        const int nblk = (int)((rows + kRows - 1) / kRows);
-        hals_kernel<RP, MODE><<<nblk, kThreads, 0, s>>>(h);
+        const HalsArgs h = hals_args(RP, rows, r, K, b, w_side);
+        hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
         if (mid) (void)hipEventRecord(mid, s);
-
-        FinArgs f{};
-        f.part = b.part_g;
-        f.nblk = nblk;
-        f.r = r;
-        f.gram = w_side ? b.GW : b.GH;
-        f.gram_slot_stride = w_side ? gram_stride(RP) : 0;
-        f.GH = b.GH;
-        f.scratch = b.part_d;
-        f.counter = counter;
-        f.st = b.st;
-        f.trace = b.trace;
-        f.accepted = b.accepted;
-        f.beta_used = b.beta_used;
-        const int fblk = (rec_len<RP>(NG) + 15) / 16;
-        finish_kernel<RP, MODE><<<fblk, 256, 0, s>>>(f);
+        const FinArgs f = fin_args(RP, rows, r, b, w_side, counter);
+        finish_kernel<RP, MODE><<<fin_blocks(RP, NG), 256, 0, s>>>(f);
+    }
+    // Grouped half-iteration: the sweep kernel over group gh, then the
+    // finish kernel over group gf.
+    static void group(bool w_side, const Group &gh, int hblocks, const Group &gf, int fblocks,
+                      hipStream_t s)
+    {
+        if (w_side) {
+            hals_group_kernel<RP, SWEEP_W><<<hblocks, kThreads, 0, s>>>(gh);
+            finish_group_kernel<RP, SWEEP_W><<<fblocks, 256, 0, s>>>(gf);
+        } else {
+            hals_group_kernel<RP, SWEEP_H><<<hblocks, kThreads, 0, s>>>(gh);
+            finish_group_kernel<RP, SWEEP_H><<<fblocks, 256, 0, s>>>(gf);
+        }
     }
     static void sweep_h(int64_t n, int r, int K, const Buffers &b, hipStream_t s, hipEvent_t mid)
     {

@@ -115,3 +115,13 @@ def test_csr_needs_fp32_storage():
         with pytest.raises(P.NMFError) as e:
             P.Solver(X, 1, **kw)
         assert e.value.status == P.Status.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("kw", [dict(hbm_budget=0), dict(max_active=0), dict(max_active=5000),
+                                dict(check_every=0)])
+def test_batch_parameter_validation(kw):
+    args = dict(hbm_budget=1 << 20, max_active=4, check_every=1)
+    args.update(kw)
+    with pytest.raises(P.NMFError) as e:
+        P.Batch(**args)
+    assert e.value.status == P.Status.E_INVAL
