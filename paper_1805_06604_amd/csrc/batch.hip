@@ -188,7 +188,8 @@ int rank_class(int rp) { return rp / 16 - 1; }
 struct nmf_batch {
     nmf_batch_params bp{};
     int device = 0;
-    hipStream_t s = nullptr;
+    hipStream_t s = nullptr;             // admission, tables, read-back
+    hipStream_t cs[kClasses] = {};       // batch iterations, one stream per padded rank
     char *pool = nullptr;
     Arena arena;
     std::deque<Prob *> queue;
@@ -379,14 +380,15 @@ nmf_status run_iterations(nmf_batch *B, int iters)
             if (B->members[c].empty()) continue;
             const int rp = 16 * (c + 1);
             const int *nb = B->blocks[c];
+            hipStream_t cs = B->cs[c];
             BHIP(nmf::i8::launch_group(rp, group_of(B, c, 0, offsetof(Entry, pc)), nb[0],
-                                       group_of(B, c, 1, offsetof(Entry, pc)), nb[1], B->s));
+                                       group_of(B, c, 1, offsetof(Entry, pc)), nb[1], cs));
             BHIP(nmf::launch_group_sweep(rp, false, group_of(B, c, 2, offsetof(Entry, hh)), nb[2],
-                                         group_of(B, c, 3, offsetof(Entry, fh)), nb[3], B->s));
+                                         group_of(B, c, 3, offsetof(Entry, fh)), nb[3], cs));
             BHIP(nmf::i8::launch_group(rp, group_of(B, c, 4, offsetof(Entry, pa)), nb[4],
-                                       group_of(B, c, 5, offsetof(Entry, pa)), nb[5], B->s));
+                                       group_of(B, c, 5, offsetof(Entry, pa)), nb[5], cs));
             BHIP(nmf::launch_group_sweep(rp, true, group_of(B, c, 6, offsetof(Entry, hw)), nb[6],
-                                         group_of(B, c, 7, offsetof(Entry, fw)), nb[7], B->s));
+                                         group_of(B, c, 7, offsetof(Entry, fw)), nb[7], cs));
         }
     return NMF_OK;
 }
@@ -396,6 +398,7 @@ nmf_status run_iterations(nmf_batch *B, int iters)
 nmf_status retire(nmf_batch *B)
 {
     const int np = (int)B->active.size();
+    for (int c = 0; c < kClasses; ++c) BHIP(hipStreamSynchronize(B->cs[c]));
     if (np == 0) return NMF_OK;
     gather_state<<<(np + 255) / 256, 256, 0, B->s>>>(B->d_states, np, B->d_flags);
     BHIP(hipGetLastError());
@@ -459,6 +462,9 @@ nmf_status nmf_batch_create(const nmf_batch_params *bp, nmf_batch **out)
     if (hipGetDevice(&B->device) != hipSuccess ||
         hipStreamCreateWithFlags(&B->s, hipStreamNonBlocking) != hipSuccess)
         return cleanup(berr(NMF_E_DEVICE, "no usable HIP device"));
+    for (int c = 0; c < kClasses; ++c)
+        if (hipStreamCreateWithFlags(&B->cs[c], hipStreamNonBlocking) != hipSuccess)
+            return cleanup(berr(NMF_E_DEVICE, "stream creation failed"));
     if (hipMalloc(&B->pool, (size_t)bp->hbm_budget) != hipSuccess)
         return cleanup(berr(NMF_E_NOMEM, "the batch arena does not fit on the device"));
     B->arena.init(B->pool, (size_t)bp->hbm_budget);
@@ -597,6 +603,8 @@ void nmf_batch_destroy(nmf_batch *B)
 {
     if (!B) return;
     (void)hipSetDevice(B->device);
+    for (int c = 0; c < kClasses; ++c)
+        if (B->cs[c]) (void)hipStreamSynchronize(B->cs[c]);
     if (B->s) (void)hipStreamSynchronize(B->s);
     if (B->pool) (void)hipFree(B->pool);
     if (B->d_entries) (void)hipFree(B->d_entries);
@@ -605,6 +613,8 @@ void nmf_batch_destroy(nmf_batch *B)
     if (B->d_flags) (void)hipFree(B->d_flags);
     if (B->h_flags) (void)hipHostFree(B->h_flags);
     if (B->s) (void)hipStreamDestroy(B->s);
+    for (int c = 0; c < kClasses; ++c)
+        if (B->cs[c]) (void)hipStreamDestroy(B->cs[c]);
     delete B;
 }
 

@@ -88,13 +88,14 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 }
 
 // Marks this block done; returns true in every thread of the last block to
-// finish. Writes made before the call are visible to that block. The blocks
-// of a grid run on all XCDs, whose L2 caches are not coherent with one
-// another, so the counter is updated at system scope (coherent at memory);
-// the fences write back and invalidate the L2 for the data.
+// finish. The block's results must have been written by wave 0 only (which
+// alone makes them visible before the count). The blocks of a grid run on all
+// XCDs, whose L2 caches are not coherent with one another, so the counter is
+// updated at system scope (coherent at memory); the fences write back and
+// invalidate the L2 for the data.
 __device__ inline bool last_block(uint32_t *counter, int *s_flag, int nblk)
 {
-    __threadfence();
+    if (threadIdx.x < 64) __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t prev =
@@ -404,17 +405,20 @@ struct FinArgs {
     double *beta_used;
 };
 
-// Sums the per-workgroup records (16 outputs x 16 block strides per
-// workgroup; the order of every sum is fixed) into the Gram buffers: Gram,
-// inverse diagonal (0 beyond r or for a zero diagonal) and column maxima. The
-// last workgroup then forms e(k) and decides (W sides).
+// Sums the per-workgroup records (64 outputs per workgroup, each over 4
+// interleaved strides of records, combined in a fixed order) into the Gram
+// buffers: Gram, inverse diagonal (0 beyond r or for a zero diagonal) and
+// column maxima. The last workgroup then forms e(k) and decides (W sides).
+constexpr int kFinOut = 64;
+constexpr int kFinSplit = 4;
+
 template <int RP, int MODE>
 __device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
 {
     constexpr int NG = ModeInfo<MODE>::ngram;
     constexpr int GL = RP * RP + RP;
     constexpr int LREC = rec_len<RP>(NG);
-    __shared__ double sh[16][17];
+    __shared__ double sh[kFinSplit][kFinOut];
     __shared__ double shd[4];
     __shared__ int s_last;
     DevState *st = a.st;
@@ -428,21 +432,23 @@ __device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
     } else {
         slot[0] = 0;
     }
-    const int o = threadIdx.x & 15, j = threadIdx.x >> 4;
-    const int e = bid * 16 + o;
+    const int o = threadIdx.x & (kFinOut - 1), j = threadIdx.x / kFinOut;
+    const int e = bid * kFinOut + o;
     const bool is_max = e < NG * GL && (e % GL) >= RP * RP;
     double v = 0.0;
     if (e < LREC) {
-        for (int b = j; b < a.nblk; b += 16) {
-            const double x = a.part[(size_t)b * LREC + e];
+        const double *src = a.part + e;
+        for (int b = j; b < a.nblk; b += kFinSplit) {
+            const double x = src[(size_t)b * LREC];
             v = is_max ? fmax(v, x) : v + x;
         }
     }
     sh[j][o] = v;
     __syncthreads();
-    if (j == 0 && e < LREC) {
+    if (j == 0 && e < LREC) {          // wave 0
         double s = sh[0][o];
-        for (int q = 1; q < 16; ++q) s = is_max ? fmax(s, sh[q][o]) : s + sh[q][o];
+#pragma unroll
+        for (int q = 1; q < kFinSplit; ++q) s = is_max ? fmax(s, sh[q][o]) : s + sh[q][o];
         if (e < NG * GL) {
             const int gi = e / GL, w = e % GL;
             double *Gd = a.gram + slot[gi] * a.gram_slot_stride;
@@ -559,7 +565,7 @@ inline FinArgs fin_args(int rp, int64_t rows, int r, const Buffers &b, bool w_si
 
 // Blocks of the two kernels of a half-iteration.
 inline int hals_blocks(int64_t rows) { return (int)((rows + kRows - 1) / kRows); }
-inline int fin_blocks(int rp, int ngram) { return (int)((ngram * (rp * rp + rp) + 1 + 15) / 16); }
+inline int fin_blocks(int rp, int ngram) { return (int)((ngram * (rp * rp + rp) + 1 + kFinOut - 1) / kFinOut); }
 
 // Enqueues one half-iteration (or a set-up step) of one padded rank.
 template <int RP>
