@@ -276,13 +276,18 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                 // at step q, and the later coordinates correct their t. Lanes
                 // l <= q get a zero correction, so each t stops at the value
                 // its own step used.
+                // Coordinates at or beyond r (rank padding, only ever in the
+                // last block) have x = 0, a zero inverse diagonal and hence
+                // no change: their steps are skipped (a uniform branch).
                 static_for<16>([&](auto Q) {
                     constexpr int q = decltype(Q)::value;
-                    const double gq = s_tri[b][q][lr];
+                    if (b + 1 < NB || 16 * b + q < a.r) {
+                        const double gq = s_tri[b][q][lr];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const double d = fmax(fma(t[v], inv[b], xd[b][v]), 0.0) - xd[b][v];
-                        t[v] = fma(-gq, row_bcast<q>(d), t[v]);
+                        for (int v = 0; v < 4; ++v) {
+                            const double d = fmax(fma(t[v], inv[b], xd[b][v]), 0.0) - xd[b][v];
+                            t[v] = fma(-gq, row_bcast<q>(d), t[v]);
+                        }
                     }
                 });
 #pragma unroll
