@@ -68,8 +68,10 @@ __device__ __forceinline__ void static_for(F &&f)
 template <int Q>
 __device__ __forceinline__ double row_bcast(double v)
 {
-    const long b = __builtin_amdgcn_update_dpp(0L, __builtin_bit_cast(long, v), 0x150 + Q, 0xf, 0xf,
-                                               false);
+    // Every lane is written, so the "old" operand is the source itself (no
+    // extra register initialisation).
+    const long x = __builtin_bit_cast(long, v);
+    const long b = __builtin_amdgcn_update_dpp(x, x, 0x150 + Q, 0xf, 0xf, false);
     return __builtin_bit_cast(double, b);
 }
 
@@ -191,6 +193,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
     constexpr int BUF = (kWaves * 16 * XLD > kWaves * NB * 256) ? kWaves * 16 * XLD
                                                                 : kWaves * NB * 256;
     __shared__ double s_tri[MI::sweeps ? NB : 1][16][16];
+    __shared__ double s_gb[MI::sweeps ? NS : 1][MI::sweeps ? NB : 1][64];
     __shared__ double s_buf[BUF];
     __shared__ double s_cm[kWaves][NG * RP];
     __shared__ double s_s1[kWaves];
@@ -241,11 +244,14 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
         // B operands: -G(4s+g, 16b+lr); inverse diagonal of coordinate 16b+lr;
         // strictly lower in-block Gram entries, tri[b][q][l] = G(16b+l, 16b+q)
         // for l > q (0 otherwise), for the in-block corrections.
-        double gb[NS][NB], inv[NB];
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) gb[s][b] = -G[(4 * s + g) * RP + 16 * b + lr];
+        // B operands in LDS (shared by the four waves, read right before each
+        // MFMA): s_gb[s][b][lane] = -G(4s+g, 16b+lr).
+        double inv[NB];
+        for (int e = tid; e < NS * NB * 64; e += kThreads) {
+            const int sb = e >> 6, ln = e & 63;
+            const int ss = sb / NB, bb = sb % NB;
+            s_gb[ss][bb][ln] = -G[(4 * ss + (ln >> 4)) * RP + 16 * bb + (ln & 15)];
+        }
 #pragma unroll
         for (int b = 0; b < NB; ++b) inv[b] = G[RP * RP + 16 * b + lr];
         for (int e = tid; e < NB * 256; e += kThreads) {
@@ -263,31 +269,53 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
         __syncthreads();
         double *xs = s_buf + wave * 16 * XLD;
 
+        // The numerators of the next block start before the current block is
+        // updated: its MFMAs over the k-steps outside the current block are
+        // independent of the update and overlap it; the four k-steps inside
+        // follow once the block's new values are in A layout.
+        double4v tcur = {cd[0][0], cd[0][1], cd[0][2], cd[0][3]};
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            tcur = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], s_gb[s][0][lane], tcur, 0, 0, 0);
         for (int it = 0; it < a.K; ++it) {
             static_for<NB>([&](auto B) {
                 constexpr int b = decltype(B)::value;
-                // t = c_b - x G(:, b) for the 16 rows and 16 coordinates.
-                double4v t = {cd[b][0], cd[b][1], cd[b][2], cd[b][3]};
+                constexpr int nb = (b + 1) % NB;
+                // t of the next block over the k-steps outside block b, in two
+                // chains.
+                double4v tn0 = {cd[nb][0], cd[nb][1], cd[nb][2], cd[nb][3]};
+                double4v tn1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int s = 0; s < NS; ++s)
-                    t = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], gb[s][b], t, 0, 0, 0);
+                for (int s = 0; s < NS; ++s) {
+                    if (s / 4 == b) continue;
+                    const double bo = s_gb[s][nb][lane];
+                    if (s & 1) tn1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], bo, tn1, 0, 0, 0);
+                    else tn0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], bo, tn0, 0, 0, 0);
+                }
+                double4v t = tcur;
                 // Coordinates 16b .. 16b+15 in order. Every lane forms the
                 // change its coordinate would take; lane q's is the one used
                 // at step q, and the later coordinates correct their t. Lanes
                 // l <= q get a zero correction, so each t stops at the value
-                // its own step used.
-                // Coordinates at or beyond r (rank padding, only ever in the
-                // last block) have x = 0, a zero inverse diagonal and hence
-                // no change: their steps are skipped (a uniform branch).
+                // its own step used. Coordinates at or beyond r (rank padding,
+                // only ever in the last block) have x = 0, a zero inverse
+                // diagonal and hence no change: their steps are skipped (a
+                // uniform branch).
                 static_for<16>([&](auto Q) {
                     constexpr int q = decltype(Q)::value;
                     if (b + 1 < NB || 16 * b + q < a.r) {
                         const double gq = s_tri[b][q][lr];
+                        // Stage by stage over the four independent rows of
+                        // the lane, so that their latencies overlap.
+                        double d[4];
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const double d = fmax(fma(t[v], inv[b], xd[b][v]), 0.0) - xd[b][v];
-                            t[v] = fma(-gq, row_bcast<q>(d), t[v]);
-                        }
+                        for (int v = 0; v < 4; ++v) d[v] = fma(t[v], inv[b], xd[b][v]);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) d[v] = fmax(d[v], 0.0) - xd[b][v];
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) d[v] = row_bcast<q>(d[v]);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) t[v] = fma(-gq, d[v], t[v]);
                     }
                 });
 #pragma unroll
@@ -300,6 +328,12 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) xa[4 * b + s] = xs[lr * XLD + 16 * b + 4 * s + g];
                 __builtin_amdgcn_wave_barrier();
+                // The k-steps inside block b complete the next block's t.
+                tn0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[4 * b], s_gb[4 * b][nb][lane], tn0, 0, 0, 0);
+                tn1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[4 * b + 1], s_gb[4 * b + 1][nb][lane], tn1, 0, 0, 0);
+                tn0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[4 * b + 2], s_gb[4 * b + 2][nb][lane], tn0, 0, 0, 0);
+                tn1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[4 * b + 3], s_gb[4 * b + 3][nb][lane], tn1, 0, 0, 0);
+                tcur = tn0 + tn1;
             });
         }
     }
@@ -443,6 +477,7 @@ __device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
     double v = 0.0;
     if (e < LREC) {
         const double *src = a.part + e;
+#pragma unroll 8
         for (int b = j; b < a.nblk; b += kFinSplit) {
             const double x = src[(size_t)b * LREC];
             v = is_max ? fmax(v, x) : v + x;
