@@ -1,0 +1,78 @@
+"""GPU checks of the batched multi-start / parameter-grid runner (the tuning
+protocol of section 5.3): grid runs against the FP64 oracle, the full-rank
+rows of Table 4 and the low-rank ordering of Table 3, and the whole grid at
+scale."""
+import numpy as np
+import pytest
+
+import nmf_synth as S
+from parity import compare_to_oracle
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1805_06604_amd")
+from paper_1805_06604_amd import grid as G  # noqa: E402
+
+
+def test_grid_runs_match_oracle():
+    probs = [S.fullrank(s) for s in range(2)]
+    vs = [G.PLAIN, G.Variant(1, 0.75, 2.0, 1.05, 1.01), G.Variant(2, 0.25, 3.0, 1.1, 1.05),
+          G.Variant(3, 0.5, 1.5, 1.01, 1.005), G.Variant(3, 0.75, 1.5, 1.005, 1.001)]
+    print("grid parity: 5 variants x 2 data sets, 40 iterations", flush=True)
+    res = G.run(probs, vs, 40)
+    for v, row in zip(vs, res):
+        for p, g in zip(probs, row):
+            print(v.label(), f"seed={p.seed}", flush=True)
+            compare_to_oracle(p, g, 40, inner_k=10, **v.params())
+
+
+def test_table4_full_rank_rows():
+    """Table 4 prints A-HALS 0.423815 +- 1.171e-3 and E-A-HALS (hp = 3,
+    beta0 0.5, eta 1.5, gamma 1.01, gamma_bar 1.005) 0.423817 +- 1.184e-3 on
+    200 x 200 U[0,1] data with r = 20: the means over 10 seeded data sets lie
+    within 3 standard errors."""
+    probs = [S.fullrank(s) for s in range(10)]
+    vs = [G.PLAIN, G.Variant(3, 0.5, 1.5, 1.01, 1.005)]
+    print("table 4 rows: 2 variants x 10 data sets, 300 iterations", flush=True)
+    summ = G.summarize(vs, G.run(probs, vs, 300))
+    plain, ext = summ["rows"]
+    print(plain, ext, flush=True)
+    assert abs(plain["rho_mean"] - 0.423815) < 3 * 1.171e-3 / np.sqrt(10)
+    assert abs(ext["rho_mean"] - 0.423817) < 3 * 1.184e-3 / np.sqrt(10)
+
+
+def test_table3_low_rank_ordering():
+    """Table 3 (low-rank data, e_min = 0): E-A-HALS hp = 3 ends below hp = 1,
+    which ends below plain A-HALS (same parameters, same iteration budget)."""
+    probs = [S.lowrank(s, r=20) for s in range(6)]
+    vs = [G.PLAIN, G.Variant(1, 0.5, 1.5, 1.01, 1.005), G.Variant(3, 0.5, 1.5, 1.01, 1.005)]
+    print("table 3 ordering: 3 variants x 6 data sets, 300 iterations", flush=True)
+    summ = G.summarize(vs, G.run(probs, vs, 300), e_min=[0.0] * len(probs))
+    plain, hp1, hp3 = (r["E_mean"] for r in summ["rows"])
+    print(plain, hp1, hp3, flush=True)
+    assert hp3 < hp1 < plain
+
+
+def test_whole_grid_at_scale():
+    """All 109 parameter sets on 3 data sets (327 runs in one batch): every
+    run completes its iterations with a finite, nonincreasing-on-accept trace,
+    and a sample of runs matches the oracle."""
+    probs = [S.fullrank(s) for s in range(3)]
+    vs = G.grid_variants()
+    assert len(vs) == 109
+    print("whole grid: 109 variants x 3 data sets, 30 iterations", flush=True)
+    res = G.run(probs, vs, 30)
+    for row in res:
+        for g in row:
+            assert g.n_iter == 30 and np.all(np.isfinite(g.trace))
+            acc = np.flatnonzero(g.accepted) + 1
+            # accepted iterates never increase the error over the previous one
+            assert np.all(g.trace[acc] <= g.trace[acc - 1] + 1e-12)
+    summ = G.summarize(vs, res)
+    assert set(summ["best_worst"]) == {1, 2, 3}
+    rng = np.random.default_rng(0)
+    for vi in rng.choice(len(vs), size=6, replace=False):
+        v = vs[vi]
+        for pi, p in enumerate(probs[:1]):
+            print(v.label(), flush=True)
+            compare_to_oracle(p, res[vi][pi], 30, inner_k=10, **v.params())
