@@ -43,7 +43,7 @@ def lib():
             build()
         _lib = C.CDLL(LIB)
         d, i, p = C.c_double, C.c_int, C.c_void_p
-        _lib.oracle_eahals.argtypes = [p, i, p, p, p, p, p, p, p, p, p, p]
+        _lib.oracle_eahals.argtypes = [p, i, p, p, p, p, p, p, p, p, p, p, p]
         _lib.oracle_eahals.restype = i
         _lib.oracle_nnls_h.argtypes = [p, i, p, p, i]
         _lib.oracle_nnls_w.argtypes = [p, i, p, p, i]
@@ -53,6 +53,8 @@ def lib():
         _lib.oracle_rel_error.restype = d
         _lib.oracle_rel_error_remark1.argtypes = [p, i, p, p]
         _lib.oracle_rel_error_remark1.restype = d
+        _lib.oracle_beta_star.argtypes = [p, i, p, p, p]
+        _lib.oracle_beta_star.restype = d
     return _lib
 
 
@@ -80,7 +82,8 @@ class _Held:
 def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
           eta=1.5, inner_k=10, max_iter=100, tol=0.0, flags=0, replay=None):
     """Run Alg. 2 with Alg. 3 and return a dict with W, H (last accepted),
-    trace (rho(0..n_iter)), accepted, beta, margin and n_iter."""
+    trace (rho(0..n_iter)), accepted, beta, margin, beta_star (section 4,
+    per iteration) and n_iter."""
     h = _Held(X)
     W0 = np.ascontiguousarray(W0, dtype=np.float64).reshape(h.m, r)
     H0 = np.ascontiguousarray(H0, dtype=np.float64).reshape(r, h.n)
@@ -90,6 +93,7 @@ def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
     acc = np.zeros(max(max_iter, 1), dtype=np.uint8)
     beta = np.zeros(max(max_iter, 1))
     margin = np.zeros(max(max_iter, 1))
+    bstar = np.zeros(max(max_iter, 1))
     rp = None
     if replay is not None:
         rp = np.ascontiguousarray(replay, dtype=np.uint8)
@@ -100,12 +104,22 @@ def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
     nit = C.c_int(0)
     st = lib().oracle_eahals(C.byref(h.s), r, _ptr(W0), _ptr(H0), C.byref(prm),
                              _ptr(W), _ptr(H), _ptr(trace), _ptr(acc),
-                             _ptr(beta), _ptr(margin), C.byref(nit))
+                             _ptr(beta), _ptr(margin), C.byref(nit), _ptr(bstar))
     if st != OK:
         raise RuntimeError(f"oracle_eahals failed with status {st}")
     k = nit.value
     return dict(W=W, H=H, trace=trace[:k + 1], accepted=acc[:k].astype(bool),
-                beta=beta[:k], margin=margin[:k], n_iter=k)
+                beta=beta[:k], margin=margin[:k], beta_star=bstar[:k], n_iter=k)
+
+
+def beta_star(X, Wn, W, Hw):
+    """Section 4: the beta minimizing ||X - (Wn + beta (Wn - W)) Hw||_F."""
+    h = _Held(X)
+    r = Hw.shape[0]
+    Wn = np.ascontiguousarray(Wn, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    Hw = np.ascontiguousarray(Hw, dtype=np.float64)
+    return lib().oracle_beta_star(C.byref(h.s), r, _ptr(Wn), _ptr(W), _ptr(Hw))
 
 
 def nnls_h(X, W, H0, sweeps):

@@ -191,6 +191,31 @@ static double remark1_err2(int64_t m, int r, double nx2, const double *W,
     return nx2 - 2.0 * s1 + s2;
 }
 
+/* Section 4: the beta that minimizes ||X - (W_n + beta (W_n - W)) H_w||_F^2
+ * over beta. With dW = W_n - W, A = X H_w^T and B = H_w H_w^T, the objective
+ * is a quadratic in beta whose minimizer is
+ *     beta* = <A - W_n B, dW> / <dW^T dW, B>
+ * (numerator: <X - W_n H_w, dW H_w>; denominator: ||dW H_w||_F^2). Reading
+ * R16: when ||dW H_w|| = 0 there is no direction and beta* is reported as 0. */
+static double beta_star_of(int64_t m, int r, const double *A, const double *B,
+                           const double *Wn, const double *W)
+{
+    double num = 0.0, den = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        for (int k = 0; k < r; ++k) {
+            double wb = 0.0, db = 0.0;
+            for (int l = 0; l < r; ++l) {
+                wb += Wn[i * r + l] * B[l * r + k];
+                db += (Wn[i * r + l] - W[i * r + l]) * B[l * r + k];
+            }
+            const double dk = Wn[i * r + k] - W[i * r + k];
+            num += (A[i * r + k] - wb) * dk;
+            den += db * dk;
+        }
+    }
+    return den > 0.0 ? num / den : 0.0;
+}
+
 /* ---------------------------------------------------------- beta (Alg. 3) */
 
 typedef struct {
@@ -278,7 +303,8 @@ static void extrapolate(int64_t len, double beta, const double *N,
 int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
                   const double *H0, const oracle_params *p, double *W,
                   double *H, double *trace, uint8_t *accepted,
-                  double *beta_used, double *margin, int *n_iter)
+                  double *beta_used, double *margin, int *n_iter,
+                  double *beta_star)
 {
     if (!valid_matrix(X) || r < 1 || p == NULL || p->hp < 1 || p->hp > 3 ||
         p->max_iter < 0 || p->inner_k < 1)
@@ -343,6 +369,7 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         memcpy(Wn, Wy, sizeof(double) * mr);
         for (int s = 0; s < p->inner_k; ++s) hals_cols_w(m, r, A, B, Wn);
         round_f32(mr, Wn, p->flags);
+        if (beta_star) beta_star[k - 1] = beta_star_of(m, r, A, B, Wn, W);
 
         /* W_y = W_n + beta (W_n - W). */
         extrapolate(mr, beta, Wn, W, Wyn, 0);
@@ -388,6 +415,20 @@ done:
     free(Hy); free(Hn); free(Hyn); free(C);
     free(G); free(B);
     return status;
+}
+
+double oracle_beta_star(const oracle_matrix *X, int r, const double *Wn,
+                        const double *W, const double *Hw)
+{
+    if (!valid_matrix(X) || r < 1) return NAN;
+    const int64_t mr = X->m * r;
+    double *A = malloc(sizeof(double) * mr), *B = malloc(sizeof(double) * r * r);
+    if (!A || !B) { free(A); free(B); return NAN; }
+    x_ht(X, r, Hw, A);
+    gram_rows(X->n, r, Hw, B);
+    const double b = beta_star_of(X->m, r, A, B, Wn, W);
+    free(A); free(B);
+    return b;
 }
 
 /* ------------------------------------------------------------ NNLS entries */

@@ -40,6 +40,8 @@
  *   R12 tol > 0 stops after an accepted iteration k with
  *       |rho(k) - rho(k-1)| < tol; rho = e / ||X||_F.
  *   R13 The inner NNLS runs a fixed number K of HALS sweeps per block.
+ *   R16 The diagnostic beta* of section 4 (the beta minimizing
+ *       ||X - (W_n + beta (W_n - W)) H_w||_F) is 0 when (W_n - W) H_w = 0.
  */
 #ifndef NMF_ORACLE_H
 #define NMF_ORACLE_H
@@ -85,12 +87,21 @@ typedef struct {
  *   W (m*r), H (r*n): last accepted iterate;
  *   trace[0..n_iter]: rho(k) = e(k)/||X||_F (capacity max_iter+1);
  *   accepted[k-1], beta_used[k-1], margin[k-1] for k = 1..n_iter, where
- *   margin = (e(k) - e_compared)/||X||_F; each may be NULL.
+ *   margin = (e(k) - e_compared)/||X||_F, and beta_star[k-1], the beta* of
+ *   section 4 for the W_n, W and H_w of iteration k (see oracle_beta_star);
+ *   each may be NULL.
  * Returns ORACLE_OK, ORACLE_EINVAL or ORACLE_ENUMERIC. */
 int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
                   const double *H0, const oracle_params *p, double *W,
                   double *H, double *trace, uint8_t *accepted,
-                  double *beta_used, double *margin, int *n_iter);
+                  double *beta_used, double *margin, int *n_iter,
+                  double *beta_star);
+
+/* Section 4: beta* = argmin_beta ||X - (Wn + beta (Wn - W)) Hw||_F^2 =
+ * <X Hw^T - Wn Hw Hw^T, Wn - W> / <(Wn - W)^T (Wn - W), Hw Hw^T> (R16: 0 when
+ * the denominator is 0). Wn, W: m*r; Hw: r*n. NaN on invalid input. */
+double oracle_beta_star(const oracle_matrix *X, int r, const double *Wn,
+                        const double *W, const double *Hw);
 
 /* H-side NNLS by HALS: starting from H (r*n, in/out), run `sweeps` sweeps of
  * the closed-form row updates for min_{H>=0} ||X - W H||_F. */

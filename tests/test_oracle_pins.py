@@ -393,3 +393,43 @@ def test_lowrank_extrapolation_beats_plain_ahals():
         ext.append(oracle.solve(p.X, 20, p.W0, p.H0, beta0=0.5, **kw)["trace"][-1])
         plain.append(oracle.solve(p.X, 20, p.W0, p.H0, beta0=0.0, **kw)["trace"][-1])
     assert np.mean(ext) < 0.5 * np.mean(plain)
+
+
+# ------------------------------------------------------------ beta* (section 4)
+
+def test_beta_star_is_the_minimizer_of_the_extrapolated_error():
+    """beta* against a dense scan of ||X - (Wn + b (Wn - W)) Hw||_F^2 over b
+    and against the direct form <X - Wn Hw, dW Hw> / ||dW Hw||^2 (numpy)."""
+    rng = np.random.default_rng(11)
+    for trial in range(5):
+        m, n, r = 9, 7, 3
+        X = rng.random((m, n))
+        Wn, W, Hw = rng.random((m, r)), rng.random((m, r)), rng.random((r, n))
+        b = oracle.beta_star(X, Wn, W, Hw)
+        dWH = (Wn - W) @ Hw
+        R = X - Wn @ Hw
+        assert abs(b - np.sum(R * dWH) / np.sum(dWH * dWH)) < 1e-12 * max(1.0, abs(b))
+        grid = np.linspace(b - 2.0, b + 2.0, 4001)
+        f = [np.sum((X - (Wn + g * (Wn - W)) @ Hw) ** 2) for g in grid]
+        assert abs(grid[int(np.argmin(f))] - b) <= 1e-3
+
+
+def test_beta_star_without_direction_is_zero():
+    """R16: W_n = W leaves no direction; beta* is reported as 0."""
+    rng = np.random.default_rng(3)
+    X = rng.random((6, 5))
+    W = rng.random((6, 2))
+    assert oracle.beta_star(X, W, W, rng.random((2, 5))) == 0.0
+
+
+def test_beta_star_of_the_first_iteration():
+    """The solve's beta*(1) equals beta* recomputed from its own first
+    iterate: after an accepted first iteration W = W_n, H = H_n, and for
+    hp = 3 the W update used H_w = max(0, H_n + beta0 (H_n - H0))."""
+    p = S.fullrank(4, m=40, n=30, r=4)
+    out = oracle.solve(p.X, p.r, p.W0, p.H0, hp=3, beta0=0.5, max_iter=1)
+    assert out["accepted"][0]
+    H0 = p.H0.astype(np.float64)
+    Hw = np.maximum(out["H"] + 0.5 * (out["H"] - H0), 0.0)
+    b = oracle.beta_star(p.X, out["W"], p.W0.astype(np.float64), Hw)
+    assert abs(out["beta_star"][0] - b) < 1e-12 * max(1.0, abs(b))
