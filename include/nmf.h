@@ -81,6 +81,10 @@ typedef enum {
 #define NMF_FLAG_CMP_LAST_ACCEPTED 2      /* compare e(k) with the last
                                              accepted error instead of the
                                              previous computed one          */
+#define NMF_FLAG_BETA_STAR 4              /* record the diagnostic beta* of
+                                             section 4 every iteration (see
+                                             nmf_read_beta_star); does not
+                                             change the iterates            */
 
 /* Input matrix (host memory; nmf_create copies it). */
 typedef struct {
@@ -185,6 +189,15 @@ enum nmf_phase {
  * Errors: NMF_E_STATE before nmf_start, NMF_E_INVAL (iters < 1, ms NULL, or
  * fewer than iters iterations left before max_iter), NMF_E_DEVICE. */
 nmf_status nmf_profile(nmf_ctx *ctx, int32_t iters, void *stream, double *ms);
+
+/* The diagnostic of section 4: for each iteration k = 1..*n_iter, the beta
+ * that would have minimized ||X - (W_n + beta (W_n - W)) H_w||_F, i.e.
+ * beta* = <X H_w^T - W_n H_w H_w^T, W_n - W> / <(W_n - W)^T (W_n - W),
+ * H_w H_w^T>, from the W_n, W (last accepted) and H_w of that iteration (0
+ * when the denominator vanishes), into a host array of capacity cap.
+ * Errors: NMF_E_STATE unless the context was created with
+ * NMF_FLAG_BETA_STAR and started; NMF_E_INVAL for a small cap. */
+nmf_status nmf_read_beta_star(nmf_ctx *ctx, double *beta_star, int32_t cap, int32_t *n_iter);
 
 /* ------------------------------------------------------------------------
  * Batched solves (serving many independent small problems on one GPU).

@@ -3,6 +3,7 @@
 
 The Python layer only marshals arguments to libnmf.so; see binding.py.
 """
-from .binding import (FLAG_BETABAR_LAST_ACCEPTED, FLAG_CMP_LAST_ACCEPTED, PHASES, Batch,  # noqa: F401
+from .binding import (FLAG_BETA_STAR, FLAG_BETABAR_LAST_ACCEPTED, FLAG_CMP_LAST_ACCEPTED,  # noqa: F401
+                      PHASES, Batch,
                       EXPORTS, LIB_PATH, Format, NMFError, Params, Prod, Result,
                       Solver, Status, XDtype, lib, make_params, solve)

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libnmf.so")
 
 EXPORTS = ("nmf_params_default", "nmf_create", "nmf_solve", "nmf_start",
            "nmf_iterate", "nmf_read", "nmf_profile", "nmf_destroy",
-           "nmf_last_error", "nmf_batch_create", "nmf_batch_submit", "nmf_batch_step",
+           "nmf_last_error", "nmf_read_beta_star", "nmf_batch_create", "nmf_batch_submit", "nmf_batch_step",
            "nmf_batch_result", "nmf_batch_destroy")
 
 
@@ -58,6 +58,7 @@ PHASES = ("slice_w", "prod_ct", "sweep_h", "finish_h", "slice_h", "prod_a", "swe
 
 FLAG_BETABAR_LAST_ACCEPTED = 1
 FLAG_CMP_LAST_ACCEPTED = 2
+FLAG_BETA_STAR = 4
 
 
 class NMFError(RuntimeError):
@@ -119,6 +120,8 @@ def lib():
         L.nmf_destroy.restype = None
         L.nmf_last_error.argtypes = [p]
         L.nmf_last_error.restype = C.c_char_p
+        L.nmf_read_beta_star.argtypes = [p, p, i32, p]
+        L.nmf_read_beta_star.restype = i32
         L.nmf_batch_create.argtypes = [p, p]
         L.nmf_batch_create.restype = i32
         L.nmf_batch_submit.argtypes = [p, p, p, p, p, p]
@@ -264,6 +267,15 @@ class Solver:
         ms = np.zeros(len(PHASES))
         self._check(lib().nmf_profile(self._ctx, int(iters), _stream(stream), _ptr(ms)))
         return {name: float(v) for name, v in zip(PHASES, ms)}
+
+    def read_beta_star(self):
+        """nmf_read_beta_star: the beta* diagnostic of section 4 for each
+        completed iteration (the context must have FLAG_BETA_STAR)."""
+        cap = max(self.params.max_iter, 1)
+        out = np.zeros(cap)
+        nit = C.c_int32()
+        self._check(lib().nmf_read_beta_star(self._ctx, _ptr(out), cap, C.byref(nit)))
+        return out[:nit.value]
 
     def read(self, W=None, H=None, stream=None) -> Result:
         """nmf_read into host arrays, or into given torch CUDA tensors."""

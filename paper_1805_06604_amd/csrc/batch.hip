@@ -134,6 +134,7 @@ size_t layout(Prob &q, char *base)
     b.trace = (double *)take(sizeof(double) * (q.p.max_iter + 1));
     b.accepted = (uint8_t *)take((size_t)q.p.max_iter + 1);
     b.beta_used = (double *)take(sizeof(double) * (q.p.max_iter + 1));
+    b.beta_star = (double *)take(sizeof(double) * (q.p.max_iter + 1));
     b.stage = (float *)take(sizeof(float) * (m + n) * q.r);
     b.fsl = (signed char *)take((size_t)std::max(q.ldx, q.ldxt) * 4 * rp);
     b.texp = (int *)take(sizeof(int) * rp);

@@ -133,7 +133,7 @@ nmf_status check_params(const nmf_params *p)
         return fail(nullptr, NMF_E_INVAL, "x_dtype = %d unknown", p->x_dtype);
     if (p->prod < NMF_PROD_AUTO || p->prod > NMF_PROD_MFMA_FAST)
         return fail(nullptr, NMF_E_INVAL, "prod = %d unknown", p->prod);
-    if (p->flags & ~(NMF_FLAG_BETABAR_LAST_ACCEPTED | NMF_FLAG_CMP_LAST_ACCEPTED))
+    if (p->flags & ~(NMF_FLAG_BETABAR_LAST_ACCEPTED | NMF_FLAG_CMP_LAST_ACCEPTED | NMF_FLAG_BETA_STAR))
         return fail(nullptr, NMF_E_INVAL, "unknown flags 0x%x", p->flags);
     return NMF_OK;
 }
@@ -189,7 +189,7 @@ void free_all(nmf_ctx *c)
         if (p) (void)hipFree(p);
     void *ptrs[] = {c->X, c->Xt, c->zexp_x, c->zexp_xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH,
                     c->b.A, c->b.Ct, c->b.part_g, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
-                    c->b.accepted, c->b.beta_used, c->b.stage, c->b.fsl, c->b.texp};
+                    c->b.accepted, c->b.beta_used, c->b.beta_star, c->b.stage, c->b.fsl, c->b.texp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -228,6 +228,8 @@ nmf_status alloc_buffers(nmf_ctx *c)
     HIP_TRY(c, dalloc(&b.trace, (size_t)c->p.max_iter + 1));
     HIP_TRY(c, dalloc(&b.accepted, (size_t)c->p.max_iter));
     HIP_TRY(c, dalloc(&b.beta_used, (size_t)c->p.max_iter));
+    HIP_TRY(c, dalloc(&b.beta_star, (size_t)c->p.max_iter + 1));
+    HIP_TRY(c, hipMemset(b.beta_star, 0, sizeof(double) * (c->p.max_iter + 1)));
     HIP_TRY(c, dalloc(&b.stage, (size_t)(m + n) * c->r));
     if (c->prod_kernel == nmf::PK_MFMA_I8) {
         // Both products slice their factor into one shared buffer (they run in
@@ -637,6 +639,23 @@ nmf_status nmf_read(nmf_ctx *c, float *W, float *H, int32_t on_device, double *t
     if (beta && k > 0)
         HIP_TRY(c, hipMemcpy(beta, c->b.beta_used, sizeof(double) * k, hipMemcpyDeviceToHost));
     if (n_iter) *n_iter = k;
+    return NMF_OK;
+}
+
+nmf_status nmf_read_beta_star(nmf_ctx *c, double *beta_star, int32_t cap, int32_t *n_iter)
+{
+    if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");
+    if (!(c->p.flags & NMF_FLAG_BETA_STAR))
+        return fail(c, NMF_E_STATE, "the context was created without NMF_FLAG_BETA_STAR");
+    if (!c->started) return fail(c, NMF_E_STATE, "nmf_read_beta_star before a successful nmf_start");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    DevState h{};
+    HIP_TRY(c, hipMemcpy(&h, c->b.st, sizeof(h), hipMemcpyDeviceToHost));
+    if (beta_star && cap < h.k) return fail(c, NMF_E_INVAL, "cap = %d < %d", cap, h.k);
+    if (beta_star && h.k > 0)
+        HIP_TRY(c, hipMemcpy(beta_star, c->b.beta_star, sizeof(double) * h.k, hipMemcpyDeviceToHost));
+    if (n_iter) *n_iter = h.k;
     return NMF_OK;
 }
 

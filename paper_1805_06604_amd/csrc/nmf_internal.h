@@ -16,8 +16,9 @@ constexpr int kSlots = 3;
 constexpr int kRowsPerBlock = 64;
 
 // Per-workgroup record of the sweep kernels: up to two partial Gram matrices
-// with their column maxima, and one FP64 partial sum.
-__host__ __device__ constexpr int64_t sweep_record(int rp) { return 2 * (rp * rp + rp) + 1; }
+// with their column maxima, and three FP64 partial sums (<W, A>, and the
+// numerator and denominator of the beta* diagnostic).
+__host__ __device__ constexpr int64_t sweep_record(int rp) { return 2 * (rp * rp + rp) + 3; }
 
 // Slot selectors for the product kernels.
 enum FactorSel : int32_t {
@@ -141,6 +142,7 @@ struct Buffers {
     double *trace = nullptr; // max_iter + 1
     uint8_t *accepted = nullptr;
     double *beta_used = nullptr;
+    double *beta_star = nullptr; // max_iter + 1: the beta* diagnostic (when enabled)
     float *stage = nullptr;  // staging of W0 / H0 / outputs: (m + n) * r
     signed char *fsl = nullptr; // exact-integer products: the sliced factor (shared)
     int *texp = nullptr;     // and its column exponents

@@ -49,9 +49,13 @@ struct ModeInfo {
 };
 
 // Per-workgroup record: ngram x (RP*RP Gram entries, RP column maxima), then
-// <x, c>.
+// <x, c> and the numerator and denominator of the beta* diagnostic.
+constexpr int kRecTail = 3;
 template <int RP>
-__host__ __device__ constexpr int rec_len(int ngram) { return ngram * (RP * RP + RP) + 1; }
+__host__ __device__ constexpr int rec_len(int ngram) { return ngram * (RP * RP + RP) + kRecTail; }
+
+// Solver flags read on the device (the NMF_FLAG_* values of the C ABI).
+constexpr int kFlagBetaStar = 4;
 
 template <typename F, int... I>
 __device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I...>)
@@ -196,7 +200,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
     __shared__ double s_gb[MI::sweeps ? NS : 1][MI::sweeps ? NB : 1][64];
     __shared__ double s_buf[BUF];
     __shared__ double s_cm[kWaves][NG * RP];
-    __shared__ double s_s1[kWaves];
+    __shared__ double s_s1[kWaves][kRecTail];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, g = lane >> 4;
@@ -240,6 +244,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
         }
     }
 
+    double xa[NS];             // x in A layout (sweep modes)
     if constexpr (MI::sweeps) {
         // B operands: -G(4s+g, 16b+lr); inverse diagonal of coordinate 16b+lr;
         // strictly lower in-block Gram entries, tri[b][q][l] = G(16b+l, 16b+q)
@@ -259,7 +264,6 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
             s_tri[b][q][l] = (l > q) ? G[(16 * b + l) * RP + 16 * b + q] : 0.0;
         }
         // x in A layout: row lr, coordinate 4s+g.
-        double xa[NS];
         {
             const int64_t row = row0 + lr;
             const bool ok = row < a.rows;
@@ -340,6 +344,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
 
     // Epilogue: stored FP32 rows, extrapolation, Gram operands, <x, c>.
     double gw[NG][NB][4];
+    double dw[NB][4];          // W_n - W (beta* diagnostic)
     double s1 = 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -351,9 +356,11 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
             const float xn = (float)xd[b][v];
             if constexpr (MI::sweeps) {
                 float yf = 0.0f;
+                dw[b][v] = 0.0;
                 if (ok) {
                     a.fac[dst_n * a.slot_stride + off] = xn;
                     const float prev = a.fac[acc_slot * a.slot_stride + off];
+                    dw[b][v] = xd[b][v] - (double)prev;
                     double y = fma(beta, (double)xn - (double)prev, (double)xn);
                     if (MODE == SWEEP_H && hp == 3) y = fmax(y, 0.0);
                     yf = (float)y;
@@ -369,6 +376,41 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                 gw[0][b][v] = ok ? (double)xn : 0.0;
             }
             if constexpr (MI::s1) s1 = fma((double)xn, cd[b][v], s1);
+        }
+    }
+
+    // beta* of section 4 (W side, when enabled): per row, the numerator
+    // <c - x G, dW> and the denominator <dW G, dW>, from the final x (A
+    // layout, xa) and dW (moved into A layout through the wave's LDS tile).
+    double bs_num = 0.0, bs_den = 0.0;
+    if constexpr (MODE == SWEEP_W) {
+        if (st->flags & kFlagBetaStar) {
+            double *xs = s_buf + wave * 16 * XLD;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) xs[(4 * v + g) * XLD + 16 * b + lr] = dw[b][v];
+            __builtin_amdgcn_wave_barrier();
+            double da[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) da[q] = xs[lr * XLD + 4 * q + g];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                double4v t = {cd[b][0], cd[b][1], cd[b][2], cd[b][3]};
+                double4v u = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const double bo = s_gb[q][b][lane];          // -G(4q+g, 16b+lr)
+                    t = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[q], bo, t, 0, 0, 0);
+                    u = __builtin_amdgcn_mfma_f64_16x16x4f64(da[q], bo, u, 0, 0, 0);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    bs_num = fma(t[v], dw[b][v], bs_num);
+                    bs_den = fma(-u[v], dw[b][v], bs_den);
+                }
+            }
         }
     }
 
@@ -416,8 +458,16 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
     }
     if constexpr (MI::s1) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s1 += __shfl_xor(s1, off);
-        if (lane == 0) s_s1[wave] = s1;
+        for (int off = 32; off > 0; off >>= 1) {
+            s1 += __shfl_xor(s1, off);
+            bs_num += __shfl_xor(bs_num, off);
+            bs_den += __shfl_xor(bs_den, off);
+        }
+        if (lane == 0) {
+            s_s1[wave][0] = s1;
+            s_s1[wave][1] = bs_num;
+            s_s1[wave][2] = bs_den;
+        }
     }
     __syncthreads();
     for (int e = tid; e < NG * RP; e += kThreads) {
@@ -427,7 +477,11 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
         const int gi = e / RP, k = e % RP;
         rec[gi * (RP * RP + RP) + RP * RP + k] = mx;
     }
-    if (tid == 0) rec[LREC - 1] = MI::s1 ? ((s_s1[0] + s_s1[1]) + (s_s1[2] + s_s1[3])) : 0.0;
+    if (tid < kRecTail) {
+        double v = 0.0;
+        if (MI::s1) v = (s_s1[0][tid] + s_s1[1][tid]) + (s_s1[2][tid] + s_s1[3][tid]);
+        rec[LREC - kRecTail + tid] = v;
+    }
 }
 
 struct FinArgs {
@@ -436,12 +490,13 @@ struct FinArgs {
     double *gram;          // destination Gram buffers
     int64_t gram_slot_stride;
     const double *GH;      // Gram of H_w (W sides: s2)
-    double *scratch;       // one double: the summed <x, c>
+    double *scratch;       // the summed <x, c>, beta* numerator and denominator
     uint32_t *counter;
     DevState *st;
     double *trace;
     uint8_t *accepted;
     double *beta_used;
+    double *beta_star;
 };
 
 // Sums the per-workgroup records (64 outputs per workgroup, each over 4
@@ -500,7 +555,7 @@ __device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
                 Gd[RP * RP + RP + (w - RP * RP)] = s;
             }
         } else if (ModeInfo<MODE>::s1) {
-            a.scratch[0] = s;
+            a.scratch[e - NG * GL] = s;        // <x, c>, beta* numerator, denominator
         }
     }
     if (!last_block(a.counter, &s_last, nblk)) return;
@@ -512,6 +567,10 @@ __device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
         if (threadIdx.x == 0) {
             const double s1 = a.scratch[0];
             if constexpr (MODE == SWEEP_W) {
+                if (st->flags & kFlagBetaStar) {
+                    const double den = a.scratch[2];
+                    a.beta_star[st->k] = den > 0.0 ? a.scratch[1] / den : 0.0;
+                }
                 decide(st, s1, s2, a.trace, a.accepted, a.beta_used);
             } else {
                 // e(0) of Algorithm 2 through Remark 1.
@@ -600,6 +659,7 @@ inline FinArgs fin_args(int rp, int64_t rows, int r, const Buffers &b, bool w_si
     f.trace = b.trace;
     f.accepted = b.accepted;
     f.beta_used = b.beta_used;
+    f.beta_star = b.beta_star;
     return f;
 }
 

@@ -189,3 +189,29 @@ def test_device_pointer_interface_matches_host():
     np.testing.assert_array_equal(out.trace, host.trace)
     np.testing.assert_array_equal(W.cpu().numpy(), host.W)
     np.testing.assert_array_equal(H.cpu().numpy(), host.H)
+
+
+@pytest.mark.parametrize("prod", PRODS)
+@pytest.mark.parametrize("which", ["fullrank", "lowrank"])
+def test_beta_star_diagnostic(which, prod):
+    """The beta* of section 4 per iteration against the oracle's, and the
+    diagnostic leaves the iterates unchanged. Tolerance per iteration: the
+    larger of 1e-6 (1 + |beta*|) and 3x the move of the oracle's beta* when
+    its iterates are rounded to FP32 (beta* divides by ||dW H_w||^2, which
+    shrinks as the iterates settle)."""
+    p = S.fullrank(0) if which == "fullrank" else S.lowrank(0)
+    kw = dict(hp=3, **ALG)
+    print(f"case beta* {which} {prod}", flush=True)
+    with P.Solver(p.X, p.r, max_iter=30, prod=P.Prod[prod], flags=P.FLAG_BETA_STAR, **kw) as s:
+        g = s.solve(p.W0, p.H0)
+        bs = s.read_beta_star()
+    g0 = _run(p, 30, prod=P.Prod[prod], **kw)
+    assert np.array_equal(g.trace, g0.trace) and np.array_equal(g.W, g0.W)
+    ref = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=30, replay=g.accepted, **kw)
+    f32 = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=30, replay=g.accepted,
+                       flags=oracle.ROUND_F32, **kw)
+    bo, bf = ref["beta_star"], f32["beta_star"]
+    tol = np.maximum(1e-6 * (1 + np.abs(bo)), 3 * np.abs(bf - bo))
+    print("beta*", np.round(bo[:8], 4), "max dev", np.max(np.abs(bs - bo)), flush=True)
+    assert bs.shape == bo.shape
+    assert np.all(np.abs(bs - bo) <= tol), np.max(np.abs(bs - bo) / tol)
