@@ -18,6 +18,7 @@ BETABAR_LAST_ACCEPTED = 1
 CMP_LAST_ACCEPTED = 2
 ERR_REMARK1 = 4
 ROUND_F32 = 8
+EXACT_NNLS = 16
 
 _lib = None
 
@@ -53,6 +54,8 @@ def lib():
         _lib.oracle_rel_error.restype = d
         _lib.oracle_rel_error_remark1.argtypes = [p, i, p, p]
         _lib.oracle_rel_error_remark1.restype = d
+        _lib.oracle_nnls_exact_h.argtypes = [p, i, p, p]
+        _lib.oracle_nnls_exact_w.argtypes = [p, i, p, p]
         _lib.oracle_beta_star.argtypes = [p, i, p, p, p]
         _lib.oracle_beta_star.restype = d
     return _lib
@@ -130,6 +133,28 @@ def nnls_h(X, W, H0, sweeps):
     if lib().oracle_nnls_h(C.byref(h.s), r, _ptr(W), _ptr(H), sweeps) != OK:
         raise RuntimeError("oracle_nnls_h failed")
     return H
+
+
+def nnls_exact_h(X, W, H0):
+    """Exact NNLS of every column of H (warm start H0) given W."""
+    h = _Held(X)
+    r = W.shape[1]
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    H = np.array(H0, dtype=np.float64, order="C", copy=True)
+    if lib().oracle_nnls_exact_h(C.byref(h.s), r, _ptr(W), _ptr(H)) != OK:
+        raise RuntimeError("oracle_nnls_exact_h failed")
+    return H
+
+
+def nnls_exact_w(X, H, W0):
+    """Exact NNLS of every row of W (warm start W0) given H."""
+    h = _Held(X)
+    r = H.shape[0]
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    W = np.array(W0, dtype=np.float64, order="C", copy=True)
+    if lib().oracle_nnls_exact_w(C.byref(h.s), r, _ptr(H), _ptr(W)) != OK:
+        raise RuntimeError("oracle_nnls_exact_w failed")
+    return W
 
 
 def nnls_w(X, H, W0, sweeps):

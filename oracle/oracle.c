@@ -149,6 +149,122 @@ static void hals_cols_w(int64_t m, int r, const double *A, const double *B,
     }
 }
 
+/* ------------------------------------------------------- exact NNLS (ANLS) */
+
+/* Solves M z = b for the symmetric positive definite p x p matrix M (row
+ * stride p) by Cholesky factorization; M and b are overwritten. Returns 0 if
+ * a pivot is not positive (M not positive definite). */
+static int chol_solve(int p, double *M, double *b)
+{
+    for (int k = 0; k < p; ++k) {
+        double d = M[k * p + k];
+        for (int j = 0; j < k; ++j) d -= M[k * p + j] * M[k * p + j];
+        if (!(d > 0.0)) return 0;
+        d = sqrt(d);
+        M[k * p + k] = d;
+        for (int i = k + 1; i < p; ++i) {
+            double v = M[i * p + k];
+            for (int j = 0; j < k; ++j) v -= M[i * p + j] * M[k * p + j];
+            M[i * p + k] = v / d;
+        }
+    }
+    for (int i = 0; i < p; ++i) {            /* L y = b */
+        double v = b[i];
+        for (int j = 0; j < i; ++j) v -= M[i * p + j] * b[j];
+        b[i] = v / M[i * p + i];
+    }
+    for (int i = p - 1; i >= 0; --i) {       /* L^T z = y */
+        double v = b[i];
+        for (int j = i + 1; j < p; ++j) v -= M[j * p + i] * b[j];
+        b[i] = v / M[i * p + i];
+    }
+    return 1;
+}
+
+/* One exact NNLS problem, min 1/2 x^T G x - c^T x over x >= 0 (G: r x r
+ * symmetric positive semidefinite), by block principal pivoting (the
+ * active-set method that section 1 cites for ANLS): the passive set F starts
+ * from the support of the warm start x; each step solves the unconstrained
+ * problem on F and exchanges the coordinates that violate x_F >= 0 or
+ * y = G x - c >= 0 off F: all of them while the count of violations keeps
+ * dropping (or at most 3 times without progress), else only the largest
+ * index. Reading R17: a coordinate with G_kk = 0 does not enter the
+ * objective and keeps max(0, x_k). work: r*r + r doubles. */
+static void nnls_bpp(int r, const double *G, const double *c, double *x, double *work)
+{
+    double *M = work, *b = M + r * r;
+    double x0[r], y[r];
+    int F[r], map[r];
+    for (int k = 0; k < r; ++k) {
+        x0[k] = x[k] > 0.0 ? x[k] : 0.0;
+        F[k] = (G[k * r + k] > 0.0) && x[k] > 0.0;
+    }
+    int alpha = 3, best = r + 1;
+    for (int it = 0; it < 10 * r + 20; ++it) {
+        /* x_F from G_FF x_F = c_F; x = 0 off F (R17 coordinates keep x0). */
+        int p = 0;
+        for (int k = 0; k < r; ++k)
+            if (F[k]) map[p++] = k;
+        for (int i = 0; i < p; ++i) {
+            for (int j = 0; j < p; ++j) M[i * p + j] = G[map[i] * r + map[j]];
+            b[i] = c[map[i]];
+        }
+        if (p > 0 && !chol_solve(p, M, b)) break;
+        for (int k = 0; k < r; ++k) x[k] = (G[k * r + k] > 0.0) ? 0.0 : x0[k];
+        for (int i = 0; i < p; ++i) x[map[i]] = b[i];
+        int nv = 0, vmax = -1;
+        for (int k = 0; k < r; ++k) {
+            y[k] = 0.0;
+            if (!(G[k * r + k] > 0.0)) continue;
+            if (!F[k]) {
+                double g = -c[k];
+                for (int j = 0; j < r; ++j) g += G[k * r + j] * x[j];
+                y[k] = g;
+            }
+            if ((F[k] && x[k] < 0.0) || (!F[k] && y[k] < 0.0)) {
+                ++nv;
+                vmax = k;
+            }
+        }
+        if (nv == 0) break;
+        if (nv < best || alpha > 0) {
+            if (nv < best) {
+                best = nv;
+                alpha = 3;
+            } else {
+                --alpha;
+            }
+            for (int k = 0; k < r; ++k)
+                if (G[k * r + k] > 0.0 && ((F[k] && x[k] < 0.0) || (!F[k] && y[k] < 0.0)))
+                    F[k] = !F[k];
+        } else {
+            F[vmax] = !F[vmax];
+        }
+    }
+}
+
+/* Exact NNLS of every column of H (r x n) given C = W^T X and G = W^T W. */
+static void exact_rows_h(int64_t n, int r, const double *C, const double *G, double *H,
+                         double *work)
+{
+    double c[r], x[r];
+    for (int64_t j = 0; j < n; ++j) {
+        for (int k = 0; k < r; ++k) {
+            c[k] = C[(int64_t)k * n + j];
+            x[k] = H[(int64_t)k * n + j];
+        }
+        nnls_bpp(r, G, c, x, work);
+        for (int k = 0; k < r; ++k) H[(int64_t)k * n + j] = x[k];
+    }
+}
+
+/* Exact NNLS of every row of W (m x r) given A = X H^T and B = H H^T. */
+static void exact_cols_w(int64_t m, int r, const double *A, const double *B, double *W,
+                         double *work)
+{
+    for (int64_t i = 0; i < m; ++i) nnls_bpp(r, B, A + i * r, W + i * r, work);
+}
+
 /* ------------------------------------------------------------------ errors */
 
 static double explicit_err2(const oracle_matrix *X, int r, const double *W,
@@ -320,8 +436,9 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
     double *Hy = malloc(sizeof(double) * rn), *Hn = malloc(sizeof(double) * rn);
     double *Hyn = malloc(sizeof(double) * rn), *C = malloc(sizeof(double) * rn);
     double *G = malloc(sizeof(double) * r * r), *B = malloc(sizeof(double) * r * r);
+    double *work = malloc(sizeof(double) * (r * r + r));
     int status = ORACLE_OK;
-    if (!Wy || !Wn || !Wyn || !A || !Hy || !Hn || !Hyn || !C || !G || !B) {
+    if (!Wy || !Wn || !Wyn || !A || !Hy || !Hn || !Hyn || !C || !G || !B || !work) {
         status = ORACLE_ENOMEM;
         goto done;
     }
@@ -353,7 +470,8 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         wt_x(X, r, Wy, C);
         gram_cols(m, r, Wy, G);
         memcpy(Hn, Hy, sizeof(double) * rn);
-        for (int s = 0; s < p->inner_k; ++s) hals_rows_h(n, r, C, G, Hn);
+        if (p->flags & ORACLE_EXACT_NNLS) exact_rows_h(n, r, C, G, Hn, work);
+        else for (int s = 0; s < p->inner_k; ++s) hals_rows_h(n, r, C, G, Hn);
         round_f32(rn, Hn, p->flags);
 
         /* hp >= 2: extrapolate H now (hp = 3: and project). R6: for hp = 1
@@ -367,7 +485,8 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         x_ht(X, r, Hw, A);
         gram_rows(n, r, Hw, B);
         memcpy(Wn, Wy, sizeof(double) * mr);
-        for (int s = 0; s < p->inner_k; ++s) hals_cols_w(m, r, A, B, Wn);
+        if (p->flags & ORACLE_EXACT_NNLS) exact_cols_w(m, r, A, B, Wn, work);
+        else for (int s = 0; s < p->inner_k; ++s) hals_cols_w(m, r, A, B, Wn);
         round_f32(mr, Wn, p->flags);
         if (beta_star) beta_star[k - 1] = beta_star_of(m, r, A, B, Wn, W);
 
@@ -413,7 +532,7 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
 done:
     free(Wy); free(Wn); free(Wyn); free(A);
     free(Hy); free(Hn); free(Hyn); free(C);
-    free(G); free(B);
+    free(G); free(B); free(work);
     return status;
 }
 
@@ -432,6 +551,34 @@ double oracle_beta_star(const oracle_matrix *X, int r, const double *Wn,
 }
 
 /* ------------------------------------------------------------ NNLS entries */
+
+int oracle_nnls_exact_h(const oracle_matrix *X, int r, const double *W, double *H)
+{
+    if (!valid_matrix(X) || r < 1) return ORACLE_EINVAL;
+    const int64_t rn = (int64_t)r * X->n;
+    double *C = malloc(sizeof(double) * rn), *G = malloc(sizeof(double) * r * r);
+    double *work = malloc(sizeof(double) * (r * r + r));
+    if (!C || !G || !work) { free(C); free(G); free(work); return ORACLE_ENOMEM; }
+    wt_x(X, r, W, C);
+    gram_cols(X->m, r, W, G);
+    exact_rows_h(X->n, r, C, G, H, work);
+    free(C); free(G); free(work);
+    return ORACLE_OK;
+}
+
+int oracle_nnls_exact_w(const oracle_matrix *X, int r, const double *H, double *W)
+{
+    if (!valid_matrix(X) || r < 1) return ORACLE_EINVAL;
+    const int64_t mr = X->m * r;
+    double *A = malloc(sizeof(double) * mr), *B = malloc(sizeof(double) * r * r);
+    double *work = malloc(sizeof(double) * (r * r + r));
+    if (!A || !B || !work) { free(A); free(B); free(work); return ORACLE_ENOMEM; }
+    x_ht(X, r, H, A);
+    gram_rows(X->n, r, H, B);
+    exact_cols_w(X->m, r, A, B, W, work);
+    free(A); free(B); free(work);
+    return ORACLE_OK;
+}
 
 int oracle_nnls_h(const oracle_matrix *X, int r, const double *W, double *H,
                   int sweeps)

@@ -40,6 +40,8 @@
  *   R12 tol > 0 stops after an accepted iteration k with
  *       |rho(k) - rho(k-1)| < tol; rho = e / ||X||_F.
  *   R13 The inner NNLS runs a fixed number K of HALS sweeps per block.
+ *   R17 Exact NNLS (E-ANLS): a coordinate whose Gram diagonal is zero does
+ *       not enter the objective and keeps max(0, warm start), as in R10.
  *   R16 The diagnostic beta* of section 4 (the beta minimizing
  *       ||X - (W_n + beta (W_n - W)) H_w||_F) is 0 when (W_n - W) H_w = 0.
  */
@@ -63,6 +65,9 @@ extern "C" {
 #define ORACLE_ROUND_F32             8  /* round the stored iterates W_n, H_n, W_y, H_y
                                            to FP32 after each update (conditioning
                                            probe; all arithmetic stays FP64)       */
+#define ORACLE_EXACT_NNLS           16  /* E-ANLS: solve each NNLS block exactly
+                                           (block principal pivoting) instead of
+                                           inner_k HALS sweeps                     */
 
 typedef struct {
     int64_t m, n;
@@ -107,6 +112,12 @@ double oracle_beta_star(const oracle_matrix *X, int r, const double *Wn,
  * the closed-form row updates for min_{H>=0} ||X - W H||_F. */
 int oracle_nnls_h(const oracle_matrix *X, int r, const double *W, double *H,
                   int sweeps);
+
+/* Exact NNLS blocks (E-ANLS): every column of H (r*n, in: warm start, out:
+ * solution) given W, or every row of W (m*r) given H, by block principal
+ * pivoting (R17 for zero Gram diagonals). */
+int oracle_nnls_exact_h(const oracle_matrix *X, int r, const double *W, double *H);
+int oracle_nnls_exact_w(const oracle_matrix *X, int r, const double *H, double *W);
 
 /* W-side NNLS by HALS: W (m*r, in/out), H fixed. */
 int oracle_nnls_w(const oracle_matrix *X, int r, const double *H, double *W,
