@@ -189,7 +189,9 @@ static int chol_solve(int p, double *M, double *b)
  * y = G x - c >= 0 off F: all of them while the count of violations keeps
  * dropping (or at most 3 times without progress), else only the largest
  * index. Reading R17: a coordinate with G_kk = 0 does not enter the
- * objective and keeps max(0, x_k). work: r*r + r doubles. */
+ * objective and keeps max(0, x_k); if a passive-set system is singular or the
+ * step cap is reached, the last complete iterate (initially the projected warm
+ * start) is returned, projected onto x >= 0. work: r*r + r doubles. */
 static void nnls_bpp(int r, const double *G, const double *c, double *x, double *work)
 {
     double *M = work, *b = M + r * r;
@@ -198,6 +200,7 @@ static void nnls_bpp(int r, const double *G, const double *c, double *x, double 
     for (int k = 0; k < r; ++k) {
         x0[k] = x[k] > 0.0 ? x[k] : 0.0;
         F[k] = (G[k * r + k] > 0.0) && x[k] > 0.0;
+        x[k] = x0[k];
     }
     int alpha = 3, best = r + 1;
     for (int it = 0; it < 10 * r + 20; ++it) {
@@ -241,6 +244,8 @@ static void nnls_bpp(int r, const double *G, const double *c, double *x, double 
             F[vmax] = !F[vmax];
         }
     }
+    for (int k = 0; k < r; ++k)
+        if (x[k] < 0.0) x[k] = 0.0;
 }
 
 /* Exact NNLS of every column of H (r x n) given C = W^T X and G = W^T W. */

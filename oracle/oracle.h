@@ -41,7 +41,9 @@
  *       |rho(k) - rho(k-1)| < tol; rho = e / ||X||_F.
  *   R13 The inner NNLS runs a fixed number K of HALS sweeps per block.
  *   R17 Exact NNLS (E-ANLS): a coordinate whose Gram diagonal is zero does
- *       not enter the objective and keeps max(0, warm start), as in R10.
+ *       not enter the objective and keeps max(0, warm start), as in R10. A
+ *       singular passive-set system or the pivoting step cap (10 r + 20)
+ *       ends the solve with the last complete iterate projected onto x >= 0.
  *   R16 The diagnostic beta* of section 4 (the beta minimizing
  *       ||X - (W_n + beta (W_n - W)) H_w||_F) is 0 when (W_n - W) H_w = 0.
  */
