@@ -49,9 +49,17 @@ typedef enum { NMF_DENSE_ROWMAJOR = 0, NMF_CSR = 1 } nmf_format;
  * objective combination runs in FP64 whatever this is. */
 typedef enum { NMF_X_F32 = 0, NMF_X_BF16 = 1, NMF_X_F16 = 2 } nmf_xdtype;
 
-/* Inner rule of A-HALS (section 1: the rows of H are updated several times
- * before W, reusing W^T W and W^T X). FIXED runs inner_k sweeps per block. */
-typedef enum { NMF_INNER_FIXED = 0 } nmf_inner;
+/* How each block subproblem (the NNLS in H with W fixed, then in W with H
+ * fixed) is solved. FIXED: A-HALS, inner_k HALS sweeps per block (section 1:
+ * the rows of H are updated several times before W, reusing W^T W and W^T X),
+ * giving E-A-HALS. EXACT: ANLS, every row's NNLS solved exactly by block
+ * principal pivoting (section 1, the active-set method it cites) from the
+ * extrapolated warm start, giving E-ANLS; inner_k is then ignored (it must
+ * still lie in range). A coordinate with a zero Gram diagonal keeps its warm
+ * start projected onto x >= 0; a singular passive-set system or the pivoting
+ * cap of 10 r + 20 steps returns the last complete iterate projected onto
+ * x >= 0. EXACT is not available to batched solves. */
+typedef enum { NMF_INNER_FIXED = 0, NMF_INNER_EXACT = 1 } nmf_inner;
 
 /* How the two O(mnr) products X^T W and X H^T are computed. Whatever the
  * choice, the products are summed over K-chunks in FP64, and the HALS sweeps,

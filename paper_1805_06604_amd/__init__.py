@@ -5,5 +5,5 @@ The Python layer only marshals arguments to libnmf.so; see binding.py.
 """
 from .binding import (FLAG_BETA_STAR, FLAG_BETABAR_LAST_ACCEPTED, FLAG_CMP_LAST_ACCEPTED,  # noqa: F401
                       PHASES, Batch,
-                      EXPORTS, LIB_PATH, Format, NMFError, Params, Prod, Result,
+                      EXPORTS, LIB_PATH, Format, Inner, NMFError, Params, Prod, Result,
                       Solver, Status, XDtype, lib, make_params, solve)

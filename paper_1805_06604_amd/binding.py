@@ -45,6 +45,11 @@ class XDtype(enum.IntEnum):
     F16 = 2
 
 
+class Inner(enum.IntEnum):
+    FIXED = 0      # inner_k HALS sweeps per block (E-A-HALS)
+    EXACT = 1      # exact NNLS per row by block principal pivoting (E-ANLS)
+
+
 class Prod(enum.IntEnum):
     AUTO = 0
     VALU = 1
@@ -174,8 +179,8 @@ class Solver:
 
     ``X`` is a float32 (m, n) numpy array, or an object with ``m, n,
     row_ptr, col_idx, val`` (CSR). Keyword arguments set nmf_params fields
-    (hp, beta0, gamma, gamma_bar, eta, inner_k, max_iter, tol, x_dtype,
-    prod, flags)."""
+    (hp, beta0, gamma, gamma_bar, eta, inner_rule, inner_k, max_iter, tol,
+    x_dtype, prod, flags)."""
 
     def __init__(self, X, r, **params):
         self._ctx = C.c_void_p()

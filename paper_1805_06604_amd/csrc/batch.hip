@@ -356,10 +356,15 @@ nmf_status rebuild(nmf_batch *B)
             }
         }
     }
-    BHIP(hipMemcpy(B->d_entries, ent.data(), sizeof(Entry) * ent.size(), hipMemcpyHostToDevice));
-    BHIP(hipMemcpy(B->d_prefix, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice));
+    // On the batch stream, complete before any grouped launch reads the tables
+    // (the class streams do not order with the legacy default stream).
+    BHIP(hipMemcpyAsync(B->d_entries, ent.data(), sizeof(Entry) * ent.size(), hipMemcpyHostToDevice,
+                        B->s));
+    BHIP(hipMemcpyAsync(B->d_prefix, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice, B->s));
     if (!sts.empty())
-        BHIP(hipMemcpy(B->d_states, sts.data(), sizeof(DevState *) * sts.size(), hipMemcpyHostToDevice));
+        BHIP(hipMemcpyAsync(B->d_states, sts.data(), sizeof(DevState *) * sts.size(),
+                            hipMemcpyHostToDevice, B->s));
+    BHIP(hipStreamSynchronize(B->s));
     B->dirty = false;
     return NMF_OK;
 }
@@ -492,6 +497,8 @@ nmf_status nmf_batch_submit(nmf_batch *B, const nmf_matrix *X, const nmf_params 
         return berr(NMF_E_UNSUPPORTED, "batched solves take dense X");
     if (p->x_dtype != NMF_X_F32)
         return berr(NMF_E_UNSUPPORTED, "batched solves keep X in FP32 (exact-integer products)");
+    if (p->inner_rule != NMF_INNER_FIXED)
+        return berr(NMF_E_UNSUPPORTED, "batched solves run the fixed inner rule (A-HALS)");
     if (!W0 || !H0) return berr(NMF_E_INVAL, "W0 and H0 must not be NULL");
     const int64_t m = X->m, n = X->n;
     const int r = p->r;

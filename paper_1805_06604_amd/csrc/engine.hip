@@ -121,7 +121,7 @@ nmf_status check_params(const nmf_params *p)
         return fail(nullptr, NMF_E_INVAL,
                     "need 1 < gamma_bar < gamma < eta (got %g, %g, %g)", p->gamma_bar,
                     p->gamma, p->eta);
-    if (p->inner_rule != NMF_INNER_FIXED)
+    if (p->inner_rule != NMF_INNER_FIXED && p->inner_rule != NMF_INNER_EXACT)
         return fail(nullptr, NMF_E_UNSUPPORTED, "inner_rule %d is not provided", p->inner_rule);
     if (p->inner_k < 1 || p->inner_k > 1000)
         return fail(nullptr, NMF_E_INVAL, "inner_k = %d must lie in 1..1000", p->inner_k);
@@ -216,20 +216,20 @@ nmf_status alloc_buffers(nmf_ctx *c)
     HIP_TRY(c, dalloc(&b.A, (size_t)c->pa.nsplit * b.m_pad * rp));
     HIP_TRY(c, dalloc(&b.Ct, (size_t)c->pc.nsplit * b.n_pad * rp));
     // Rows that no product writes (padding; empty rows of a sparse X) read as 0.
-    HIP_TRY(c, hipMemset(b.A, 0, sizeof(double) * c->pa.nsplit * b.m_pad * rp));
-    HIP_TRY(c, hipMemset(b.Ct, 0, sizeof(double) * c->pc.nsplit * b.n_pad * rp));
+    HIP_TRY(c, hipMemsetAsync(b.A, 0, sizeof(double) * c->pa.nsplit * b.m_pad * rp, c->own));
+    HIP_TRY(c, hipMemsetAsync(b.Ct, 0, sizeof(double) * c->pc.nsplit * b.n_pad * rp, c->own));
     c->pa.Y = b.A;
     c->pc.Y = b.Ct;
     HIP_TRY(c, dalloc(&b.part_g, (size_t)(nblk * rec)));
     HIP_TRY(c, dalloc(&b.part_d, (size_t)1024));
     HIP_TRY(c, dalloc(&b.counters, (size_t)nmf::CNT_N));
-    HIP_TRY(c, hipMemset(b.counters, 0, sizeof(uint32_t) * nmf::CNT_N));
+    HIP_TRY(c, hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * nmf::CNT_N, c->own));
     HIP_TRY(c, dalloc(&b.st, 1));
     HIP_TRY(c, dalloc(&b.trace, (size_t)c->p.max_iter + 1));
     HIP_TRY(c, dalloc(&b.accepted, (size_t)c->p.max_iter));
     HIP_TRY(c, dalloc(&b.beta_used, (size_t)c->p.max_iter));
     HIP_TRY(c, dalloc(&b.beta_star, (size_t)c->p.max_iter + 1));
-    HIP_TRY(c, hipMemset(b.beta_star, 0, sizeof(double) * (c->p.max_iter + 1)));
+    HIP_TRY(c, hipMemsetAsync(b.beta_star, 0, sizeof(double) * (c->p.max_iter + 1), c->own));
     HIP_TRY(c, dalloc(&b.stage, (size_t)(m + n) * c->r));
     if (c->prod_kernel == nmf::PK_MFMA_I8) {
         // Both products slice their factor into one shared buffer (they run in
@@ -238,8 +238,8 @@ nmf_status alloc_buffers(nmf_ctx *c)
         HIP_TRY(c, dalloc(&b.texp, (size_t)rp));
     }
     // Zero the factor slots once so that no slot ever holds garbage padding.
-    HIP_TRY(c, hipMemset(b.Wf, 0, sizeof(float) * nmf::kSlots * m * rp));
-    HIP_TRY(c, hipMemset(b.Hf, 0, sizeof(float) * nmf::kSlots * n * rp));
+    HIP_TRY(c, hipMemsetAsync(b.Wf, 0, sizeof(float) * nmf::kSlots * m * rp, c->own));
+    HIP_TRY(c, hipMemsetAsync(b.Hf, 0, sizeof(float) * nmf::kSlots * n * rp, c->own));
     return NMF_OK;
 }
 
@@ -251,11 +251,11 @@ nmf_status upload_dense(nmf_ctx *c, const nmf_matrix *X)
     const size_t xtsz = (size_t)c->b.n_pad * c->ldxt * xbytes(xd);
     HIP_TRY(c, hipMalloc(&c->X, xsz));
     HIP_TRY(c, hipMalloc(&c->Xt, xtsz));
-    HIP_TRY(c, hipMemset(c->X, 0, xsz));
-    HIP_TRY(c, hipMemset(c->Xt, 0, xtsz));
+    HIP_TRY(c, hipMemsetAsync(c->X, 0, xsz, c->own));
+    HIP_TRY(c, hipMemsetAsync(c->Xt, 0, xtsz, c->own));
     float *src = nullptr;
     HIP_TRY(c, dalloc(&src, (size_t)cnt));
-    hipError_t e = hipMemcpy(src, X->dense, sizeof(float) * cnt, hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpyAsync(src, X->dense, sizeof(float) * cnt, hipMemcpyHostToDevice, c->own);
     if (e == hipSuccess)
         e = nmf::launch_convert_x(src, c->m, c->n, xd, c->X, c->ldx, c->Xt, c->ldxt, c->own);
     double *nx2 = nullptr;
@@ -274,12 +274,12 @@ nmf_status upload_dense(nmf_ctx *c, const nmf_matrix *X)
         void *xs = nullptr, *xts = nullptr;
         HIP_TRY(c, hipMalloc(&xs, (size_t)c->b.m_pad * c->ldx * 4));
         HIP_TRY(c, hipMalloc(&xts, (size_t)c->b.n_pad * c->ldxt * 4));
-        HIP_TRY(c, hipMemset(xs, 0, (size_t)c->b.m_pad * c->ldx * 4));
-        HIP_TRY(c, hipMemset(xts, 0, (size_t)c->b.n_pad * c->ldxt * 4));
+        HIP_TRY(c, hipMemsetAsync(xs, 0, (size_t)c->b.m_pad * c->ldx * 4, c->own));
+        HIP_TRY(c, hipMemsetAsync(xts, 0, (size_t)c->b.n_pad * c->ldxt * 4, c->own));
         HIP_TRY(c, dalloc(&c->zexp_x, (size_t)c->b.m_pad));
         HIP_TRY(c, dalloc(&c->zexp_xt, (size_t)c->b.n_pad));
-        HIP_TRY(c, hipMemset(c->zexp_x, 0, sizeof(int) * c->b.m_pad));
-        HIP_TRY(c, hipMemset(c->zexp_xt, 0, sizeof(int) * c->b.n_pad));
+        HIP_TRY(c, hipMemsetAsync(c->zexp_x, 0, sizeof(int) * c->b.m_pad, c->own));
+        HIP_TRY(c, hipMemsetAsync(c->zexp_xt, 0, sizeof(int) * c->b.n_pad, c->own));
         HIP_TRY(c, nmf::i8::slice_rows(c->X, xd, c->m, c->n, c->ldx, c->ldx, xs, c->zexp_x, c->own));
         HIP_TRY(c, nmf::i8::slice_rows(c->Xt, xd, c->n, c->m, c->ldxt, c->ldxt, xts, c->zexp_xt,
                                        c->own));
@@ -300,7 +300,7 @@ hipError_t to_device(nmf_ctx *c, const T *h, size_t count, const T **out)
     hipError_t e = dalloc(&d, count);
     if (e != hipSuccess) return e;
     c->extra.push_back(d);
-    if (count) e = hipMemcpy(d, h, sizeof(T) * count, hipMemcpyHostToDevice);
+    if (count) e = hipMemcpyAsync(d, h, sizeof(T) * count, hipMemcpyHostToDevice, c->own);
     *out = d;
     return e;
 }
@@ -386,6 +386,7 @@ nmf_status upload_csr(nmf_ctx *c, const nmf_matrix *X)
 nmf_status enqueue_iteration(nmf_ctx *c, hipStream_t s, hipEvent_t *ev = nullptr)
 {
     const int rp = c->rp, xd = c->p.x_dtype, pk = c->prod_kernel;
+    const bool exact = c->p.inner_rule == NMF_INNER_EXACT;
     Buffers &b = c->b;
     auto e = [&](int i) { return ev ? ev[i] : nullptr; };
     // a1: C^T = X^T W_y ; a2-a4: H sweeps + epilogue ; a5: A = X H_w^T ;
@@ -393,11 +394,11 @@ nmf_status enqueue_iteration(nmf_ctx *c, hipStream_t s, hipEvent_t *ev = nullptr
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SLICE_W], s));
     HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pc, s, e(NMF_PHASE_PROD_CT)));
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SWEEP_H], s));
-    HIP_TRY(c, nmf::launch_sweep_h(rp, c->n, c->r, c->p.inner_k, b, s, e(NMF_PHASE_FINISH_H)));
+    HIP_TRY(c, nmf::launch_sweep_h(rp, c->n, c->r, c->p.inner_k, exact, b, s, e(NMF_PHASE_FINISH_H)));
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SLICE_H], s));
     HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pa, s, e(NMF_PHASE_PROD_A)));
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SWEEP_W], s));
-    HIP_TRY(c, nmf::launch_sweep_w(rp, c->m, c->r, c->p.inner_k, b, s, e(NMF_PHASE_FINISH_W)));
+    HIP_TRY(c, nmf::launch_sweep_w(rp, c->m, c->r, c->p.inner_k, exact, b, s, e(NMF_PHASE_FINISH_W)));
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_COUNT], s));
     return NMF_OK;
 }
@@ -523,6 +524,10 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
     if (st == NMF_OK && !(c->nx2 > 0.0))
         st = fail(c, NMF_E_INVAL, "X is zero: the relative error is undefined");
     if (st == NMF_OK) st = build_graph(c);
+    // Every set-up step ran on the context's stream; finish them before any
+    // other stream may touch the buffers.
+    if (st == NMF_OK && hipStreamSynchronize(c->own) != hipSuccess)
+        st = fail(c, NMF_E_DEVICE, "set-up on the device failed");
     if (st != NMF_OK) {
         g_err = c->err;
         free_all(c);

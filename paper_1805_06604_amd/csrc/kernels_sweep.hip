@@ -74,17 +74,17 @@ __global__ void unpack_kernel(int rp, int64_t m, int64_t n, int r,
     default: return hipErrorInvalidValue;                         \
     }
 
-hipError_t launch_sweep_h(int rp, int64_t n, int r, int inner_k, const Buffers &b,
+hipError_t launch_sweep_h(int rp, int64_t n, int r, int inner_k, bool exact, const Buffers &b,
                           hipStream_t s, hipEvent_t mid)
 {
-    NMF_RP_CALL(rp, sweep_h, n, r, inner_k, b, s, mid);
+    NMF_RP_CALL(rp, sweep_h, n, r, inner_k, exact, b, s, mid);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_w(int rp, int64_t m, int r, int inner_k, const Buffers &b,
+hipError_t launch_sweep_w(int rp, int64_t m, int r, int inner_k, bool exact, const Buffers &b,
                           hipStream_t s, hipEvent_t mid)
 {
-    NMF_RP_CALL(rp, sweep_w, m, r, inner_k, b, s, mid);
+    NMF_RP_CALL(rp, sweep_w, m, r, inner_k, exact, b, s, mid);
     return hipGetLastError();
 }
 

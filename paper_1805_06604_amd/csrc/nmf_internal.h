@@ -182,9 +182,11 @@ __device__ inline int group_find(const Group &g, int b, int *local, int *count)
 hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hipStream_t s,
                           hipEvent_t mid = nullptr);
 
-hipError_t launch_sweep_h(int rp, int64_t n, int r, int inner_k, const Buffers &b,
+// A half-iteration: the factor update (inner_k HALS sweeps, or with `exact`
+// the exact NNLS solve of every row), its epilogue and its finish step.
+hipError_t launch_sweep_h(int rp, int64_t n, int r, int inner_k, bool exact, const Buffers &b,
                           hipStream_t s, hipEvent_t mid = nullptr);
-hipError_t launch_sweep_w(int rp, int64_t m, int r, int inner_k, const Buffers &b,
+hipError_t launch_sweep_w(int rp, int64_t m, int r, int inner_k, bool exact, const Buffers &b,
                           hipStream_t s, hipEvent_t mid = nullptr);
 
 // Set-up of e(0): Gram of H0 (slot 0) into GH, then Gram of W0 (slot 0) into

@@ -1,0 +1,200 @@
+// Exact NNLS blocks of E-ANLS (arXiv 1805.06604, section 1: ANLS solves each
+// block subproblem of Algorithm 1 exactly, with the active-set method of Kim
+// and Park; Algorithm 2 extrapolates around it).
+//
+// Each factor row is one problem min 1/2 x^T G x - c^T x over x >= 0, with G
+// the Gram matrix of the fixed factor (shared by all rows) and c the row of
+// the linear term. Block principal pivoting: the passive set starts at the
+// support of the warm start (the extrapolated iterate); each step solves the
+// unconstrained problem on the passive set and exchanges the coordinates that
+// violate x_F >= 0 on it or y = G x - c >= 0 off it: all of them while the
+// number of violations drops (or up to three times without progress), else
+// only the largest index.
+//
+// Layout: a row's problem lives in one segment of a wave (16, 32 or 64 lanes;
+// lane k = coordinate k), lane k holding row k of the passive-set system in
+// registers. The system is solved by symmetric Gaussian elimination (LDL^T,
+// no square root): pivot p needs column p in the trailing rows, which by
+// symmetry is register p of every lane, exchanged through LDS (one write,
+// broadcast reads). A pivot that is passive in no segment of the wave is
+// skipped. Back substitution goes row by row with one broadcast per step.
+// G sits in LDS, shared by the four waves of a workgroup.
+//
+// A coordinate with a zero Gram diagonal does not enter the objective and
+// keeps max(0, warm start); a singular passive-set system (a pivot <= 0) or
+// the step cap 10 r + 20 ends the solve with the last complete iterate,
+// projected onto x >= 0.
+#pragma once
+
+#include "sweep_impl.h"
+
+namespace nmf {
+namespace sweep {
+
+template <int RP>
+struct ExactShape {
+    static constexpr int SEG = RP <= 16 ? 16 : RP <= 32 ? 32 : 64;   // lanes per problem
+    static constexpr int NSEG = 64 / SEG;                             // problems per wave
+};
+
+template <int RP, int MODE>
+__device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
+{
+    constexpr int SEG = ExactShape<RP>::SEG, NSEG = ExactShape<RP>::NSEG;
+    constexpr int PASSES = kExactRows / (kWaves * NSEG);
+    static_assert(PASSES * kWaves * NSEG == kExactRows, "rows per workgroup");
+    __shared__ double s_g[RP * RP];
+    __shared__ double s_col[kWaves][64];
+    __shared__ double s_b[kWaves][64];
+    __shared__ double s_x[kWaves][64];
+    __shared__ double s_d[kWaves][64];
+
+    DevState *st = a.st;
+    if (st->done) return;
+    int src, dst;
+    const double *G = a.gram;
+    if constexpr (MODE == SWEEP_H) {
+        src = st->h_y; dst = st->h_n;
+        G += (int64_t)st->w_y * a.gram_slot_stride;
+    } else {
+        src = st->w_y; dst = st->w_n;
+    }
+    for (int e = threadIdx.x; e < RP * RP; e += kThreads) s_g[e] = G[e];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int seg = lane / SEG, k = lane % SEG, sb = seg * SEG;
+    const int kk = k < RP ? k : RP - 1;          // LDS column of idle lanes (RP = 48)
+    const uint64_t segmask = SEG == 64 ? ~0ull : ((1ull << SEG) - 1);
+    const int cap = 10 * a.r + 20;
+    const float *xsrc = a.fac + src * a.slot_stride;
+    float *xdst = a.fac + dst * a.slot_stride;
+    double *col = s_col[wave], *bb = s_b[wave], *xs = s_x[wave], *sd = s_d[wave];
+
+    for (int pass = 0; pass < PASSES; ++pass) {
+        const int64_t row = (int64_t)bid * kExactRows + (pass * kWaves + wave) * NSEG + seg;
+        const bool valid = row < a.rows && k < RP;
+        double c = 0.0, w = 0.0;
+        if (valid) {
+            const double *p = a.lin + row * RP + k;
+            c = p[0];
+            for (int sp = 1; sp < a.nsplit; ++sp) c += p[sp * a.split_stride];
+            w = (double)xsrc[row * RP + k];
+        }
+        const bool pos = valid && k < a.r && s_g[kk * RP + kk] > 0.0;
+        const double x0 = fmax(w, 0.0);
+        double x = x0;                           // last complete iterate
+        bool F = pos && w > 0.0;                 // passive set
+        bool done = !(row < a.rows);             // uniform over the segment
+        int alpha = 3, best = RP + 1;
+        for (int it = 0; it < cap; ++it) {
+            if (__ballot(!done) == 0) break;
+            // The lane's coordinate, opaque to the compiler, so that the
+            // comparisons with the pivot below are formed where they are used
+            // rather than kept live for every pivot across the whole loop.
+            int kl = k;
+            asm volatile("" : "+v"(kl));
+            const uint64_t fw = __ballot(F);
+            const uint64_t fm = (fw >> sb) & segmask;        // this segment's set
+            uint64_t fu = 0;                                 // union over segments
+#pragma unroll
+            for (int q = 0; q < NSEG; ++q) fu |= (fw >> (q * SEG)) & segmask;
+
+            // Row k of the system: G restricted to the passive set (rows and
+            // columns off it are zero; their pivots are skipped and their
+            // solution is 0).
+            double M[RP];
+            static_for<RP>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                const double gj = s_g[j * RP + kk];
+                M[j] = (F && ((fm >> j) & 1)) ? gj : 0.0;
+            });
+            double b = F ? c : 0.0;
+            bool fail = false;
+
+            // Elimination: rows k > p lose f_k times row p, f_k = S(k,p) / S(p,p);
+            // row p of the trailing matrix is column p by symmetry.
+            static_for<RP>([&](auto P) {
+                constexpr int p = decltype(P)::value;
+                if ((fu >> p) & 1) {
+                    col[lane] = M[p];
+                    bb[lane] = b;
+                    __builtin_amdgcn_wave_barrier();
+                    const double d = col[sb + p], bp = bb[sb + p];
+                    const bool pp = (fm >> p) & 1;
+                    const bool ok = d > 0.0;
+                    if (pp && !ok) fail = true;
+                    const double f = (pp && ok && kl > p) ? M[p] / d : 0.0;
+                    sd[sb + p] = d;
+                    static_for<RP - p - 1>([&](auto J) {
+                        constexpr int j = p + 1 + decltype(J)::value;
+                        M[j] = fma(-f, col[sb + j], M[j]);
+                    });
+                    b = fma(-f, bp, b);
+                    __builtin_amdgcn_wave_barrier();
+                }
+            });
+
+            // Back substitution: x_p = (b_p - sum_{j > p} S(p,j) x_j) / S(p,p),
+            // the sum accumulated in lane p as the later x_j become known; a
+            // lane's value is final once its own step is done.
+            const double rdk = F ? 1.0 / sd[sb + kk] : 1.0;
+            double acc = 0.0;
+            static_for<RP>([&](auto P) {
+                constexpr int p = RP - 1 - decltype(P)::value;
+                if ((fu >> p) & 1) {
+                    xs[lane] = (b - acc) * rdk;
+                    __builtin_amdgcn_wave_barrier();
+                    const double xp = xs[sb + p];
+                    acc = fma(kl < p ? M[p] : 0.0, xp, acc);
+                    __builtin_amdgcn_wave_barrier();
+                }
+            });
+            const double sol = (b - acc) * rdk;
+            const double xn = pos ? (F ? sol : 0.0) : x0;
+
+            // Dual variables y = G x - c and the infeasible coordinates.
+            xs[lane] = xn;
+            __builtin_amdgcn_wave_barrier();
+            double y = -c;
+            static_for<RP>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                y = fma(s_g[j * RP + kk], xs[sb + j], y);
+            });
+            __builtin_amdgcn_wave_barrier();
+            const bool viol = pos && (F ? xn < 0.0 : y < 0.0);
+            const uint64_t vm = (__ballot(viol) >> sb) & segmask;
+            const int nv = __popcll(vm);
+            if (!done) {
+                if (fail) {
+                    done = true;
+                } else {
+                    x = xn;
+                    if (nv == 0) {
+                        done = true;
+                    } else if (nv < best || alpha > 0) {
+                        if (nv < best) {
+                            best = nv;
+                            alpha = 3;
+                        } else {
+                            --alpha;
+                        }
+                        if (viol) F = !F;
+                    } else if (k == 63 - __clzll(vm)) {
+                        F = !F;
+                    }
+                }
+            }
+        }
+        if (valid) xdst[row * RP + k] = (float)fmax(x, 0.0);
+    }
+}
+
+template <int RP, int MODE>
+__global__ __launch_bounds__(kThreads, 2) void exact_kernel(HalsArgs a)
+{
+    exact_body<RP, MODE>(a, blockIdx.x);
+}
+
+}  // namespace sweep
+}  // namespace nmf

@@ -177,6 +177,8 @@ struct HalsArgs {
     int64_t gram_slot_stride;   // > 0: slot chosen by w_y (H update)
     double *part;          // per-workgroup records
     DevState *st;
+    int exact;             // sweep modes: start from the new-iterate slot, which
+                           // the exact NNLS solve has filled (used with K = 0)
 };
 
 // SETUP_H / SETUP_W: Gram (and for W, <W0, A>) of slot 0.
@@ -220,6 +222,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
         } else {
             src = st->w_y; dst_n = st->w_n; dst_y = st->w_yn; acc_slot = st->w_acc;
         }
+        if (a.exact) src = dst_n;
     }
     const float *xsrc = a.fac + src * a.slot_stride;
 
@@ -617,6 +620,14 @@ __global__ __launch_bounds__(256) void finish_group_kernel(Group g)
     finish_body<RP, MODE>(*reinterpret_cast<const FinArgs *>(g.base + (size_t)p * g.stride), lb, cnt);
 }
 
+// Exact NNLS solve of every factor row (E-ANLS), defined in nnls_exact.h:
+// warm start from the extrapolated slot, solution into the new-iterate slot;
+// kExactRows factor rows per workgroup of kThreads.
+constexpr int kExactRows = 32;
+template <int RP, int MODE>
+__global__ __launch_bounds__(kThreads, 2) void exact_kernel(HalsArgs a);
+inline int exact_blocks(int64_t rows) { return (int)((rows + kExactRows - 1) / kExactRows); }
+
 // Argument records of one half-iteration (or set-up step) of one problem.
 inline HalsArgs hals_args(int rp, int64_t rows, int r, int K, const Buffers &b, bool w_side)
 {
@@ -665,17 +676,26 @@ inline FinArgs fin_args(int rp, int64_t rows, int r, const Buffers &b, bool w_si
 
 // Blocks of the two kernels of a half-iteration.
 inline int hals_blocks(int64_t rows) { return (int)((rows + kRows - 1) / kRows); }
-inline int fin_blocks(int rp, int ngram) { return (int)((ngram * (rp * rp + rp) + 1 + kFinOut - 1) / kFinOut); }
+inline int fin_blocks(int rp, int ngram) { return (int)((ngram * (rp * rp + rp) + kRecTail + kFinOut - 1) / kFinOut); }
 
 // Enqueues one half-iteration (or a set-up step) of one padded rank.
 template <int RP>
 struct Launch {
+    // exact (sweep modes): the exact NNLS solve, then the sweep kernel with
+    // no sweeps for the epilogue.
     template <int MODE>
     static void run(int64_t rows, int r, int K, const Buffers &b, bool w_side, uint32_t *counter,
-                    hipStream_t s, hipEvent_t mid = nullptr)
+                    hipStream_t s, hipEvent_t mid = nullptr, bool exact = false)
     {
         constexpr int NG = ModeInfo<MODE>::ngram;
-        const HalsArgs h = hals_args(RP, rows, r, K, b, w_side);
+        HalsArgs h = hals_args(RP, rows, r, K, b, w_side);
+        if constexpr (ModeInfo<MODE>::sweeps) {
+            if (exact) {
+                exact_kernel<RP, MODE><<<exact_blocks(rows), kThreads, 0, s>>>(h);
+                h.K = 0;
+                h.exact = 1;
+            }
+        }
         hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
         if (mid) (void)hipEventRecord(mid, s);
         const FinArgs f = fin_args(RP, rows, r, b, w_side, counter);
@@ -694,13 +714,15 @@ struct Launch {
             finish_group_kernel<RP, SWEEP_H><<<fblocks, 256, 0, s>>>(gf);
         }
     }
-    static void sweep_h(int64_t n, int r, int K, const Buffers &b, hipStream_t s, hipEvent_t mid)
+    static void sweep_h(int64_t n, int r, int K, bool exact, const Buffers &b, hipStream_t s,
+                        hipEvent_t mid)
     {
-        run<SWEEP_H>(n, r, K, b, false, b.counters + CNT_H, s, mid);
+        run<SWEEP_H>(n, r, K, b, false, b.counters + CNT_H, s, mid, exact);
     }
-    static void sweep_w(int64_t m, int r, int K, const Buffers &b, hipStream_t s, hipEvent_t mid)
+    static void sweep_w(int64_t m, int r, int K, bool exact, const Buffers &b, hipStream_t s,
+                        hipEvent_t mid)
     {
-        run<SWEEP_W>(m, r, K, b, true, b.counters + CNT_W, s, mid);
+        run<SWEEP_W>(m, r, K, b, true, b.counters + CNT_W, s, mid, exact);
     }
     static void setup_h(int64_t n, int r, const Buffers &b, hipStream_t s)
     {

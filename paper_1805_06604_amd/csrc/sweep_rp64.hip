@@ -1,4 +1,4 @@
-// Sweep kernels for ranks padded to 64.
-#include "sweep_impl.h"
+// Sweep and exact NNLS kernels for ranks padded to 64.
+#include "nnls_exact.h"
 
 template struct nmf::sweep::Launch<64>;

@@ -57,6 +57,7 @@ def test_defaults_are_the_papers_final_parameters():
     (dict(prod=9), P.Status.E_INVAL),
     (dict(flags=8), P.Status.E_INVAL),
     (dict(inner_rule=3), P.Status.E_UNSUPPORTED),
+    (dict(inner_rule=P.Inner.EXACT, inner_k=0), P.Status.E_INVAL),
 ])
 def test_parameter_validation(kw, status):
     with pytest.raises(P.NMFError) as e:
@@ -125,3 +126,4 @@ def test_batch_parameter_validation(kw):
     with pytest.raises(P.NMFError) as e:
         P.Batch(**args)
     assert e.value.status == P.Status.E_INVAL
+
