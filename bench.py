@@ -10,7 +10,9 @@ graph launches. `roofline` covers the dominant kernel (the X-streaming
 product; both products of an iteration are launches of that kernel): its
 algorithmic bytes per launch over its mean duration, timed with HIP events
 recorded around each launch on the stream the library launches it on, over
-`--profile-iters` iterations run right after the timed ones. `cpu_baseline`
+`--profile-iters` iterations run right after the timed ones. `eanls` times
+E-ANLS (exact NNLS blocks) on the same workload, with the FP64 roofline of
+its exact solves. `cpu_baseline`
 times the FP64 oracle on a bounded sample of the same workload and scales it
 by the iteration's flop count to the full size.
 
@@ -64,6 +66,8 @@ def parse():
     ap.add_argument("--serve-seq", type=int, default=16,
                     help="requests of the same stream solved one at a time (baseline)")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--eanls-steps", type=int, default=20,
+                    help="timed E-ANLS iterations on the same workload (0 disables)")
     return ap.parse_args()
 
 
@@ -120,6 +124,52 @@ def cpu_baseline(args):
                        f"workload at {s}x{s}, r={args.r}, K={args.inner_k} took {t:.2f} s; scaled "
                        f"to {args.m}x{args.n} by the flop ratio {scale:.1f}; host {cpu}, "
                        f"os.cpu_count()={os.cpu_count()}")}
+
+
+FP64_VECTOR_PEAK_TFS = 78.6
+
+
+def nnls_flops(F, r):
+    """Algorithmic flops of the exact NNLS of every row of F (rows x r) with
+    final passive set the row's support, p entries: one Cholesky of the
+    passive system (p^3/3 FMA), two triangular solves (p^2) and the dual
+    check off the passive set ((r - p) p)."""
+    p = np.count_nonzero(np.asarray(F) > 0, axis=1).astype(np.float64)
+    return float(np.sum(2.0 * (p ** 3 / 3.0 + p * p + (r - p) * p)))
+
+
+def eanls(args, P, p, stream, torch):
+    """E-ANLS (every block NNLS solved exactly, hp = 1 and the E-ANLS
+    parameters of section 5.3.1) on the same resident workload."""
+    m, n, r = args.m, args.n, args.r
+    total = 5 + args.eanls_steps + args.profile_iters
+    solver = P.Solver(p.X, r, hp=1, beta0=0.5, gamma=1.1, gamma_bar=1.05, eta=1.5,
+                      inner_rule=P.Inner.EXACT, max_iter=total)
+    solver.start(p.W0, p.H0, stream=stream)
+    solver.iterate(5, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    solver.iterate(args.eanls_steps, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.eanls_steps
+    ph = solver.profile(args.profile_iters, stream=stream)
+    res = solver.read(stream=stream)
+    solver.close()
+    # The exact-solve phases include the no-sweep epilogue launch after the
+    # solve kernel; the flops are those of the final supports.
+    solve_ms = ph["sweep_h"] + ph["sweep_w"]
+    flops = nnls_flops(res.H.T, r) + nnls_flops(res.W, r)
+    achieved = flops / (solve_ms * 1e-3) / 1e12
+    return {"workload": f"planted dense {m}x{n} r={r}, E-ANLS hp=1 beta0=0.5 eta=1.5 gamma=1.1 "
+                        f"gamma_bar=1.05", "value": 1e3 / ms, "unit": "iters/s", "ms_per_step": ms,
+            "steps": args.eanls_steps, "phase_ms": ph, "rho_final": float(res.trace[-1]),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFS,
+                         "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFS,
+                         "traffic": None, "kernel": "exact NNLS solve (both sides per iteration)",
+                         "flops_per_iteration": flops, "ms_per_iteration": solve_ms}}
 
 
 def serving(args, P, S):
@@ -204,6 +254,7 @@ def main():
     xd = {"f32": P.XDtype.F32, "bf16": P.XDtype.BF16, "f16": P.XDtype.F16}[args.x_dtype]
     pm = {"auto": P.Prod.AUTO, "valu": P.Prod.VALU, "exact": P.Prod.MFMA_EXACT,
           "fast": P.Prod.MFMA_FAST}[args.prod]
+    ea = eanls(args, P, p, stream, torch) if args.eanls_steps > 0 else None
     solver = P.Solver(p.X, r, hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
                       inner_k=K, max_iter=total, x_dtype=xd, prod=pm)
     del p
@@ -262,6 +313,8 @@ def main():
                      "traffic": traffic, "kernel": "X-streaming product",
                      "bytes_per_launch": 0.5 * (bytes_ct + bytes_a), "ms_per_launch": prod_ms},
     }
+    if ea is not None:
+        out["eanls"] = ea
     if args.serve_requests > 0:
         out["serving"] = serving(args, P, S)
     if args.cpu_sample > 0:
