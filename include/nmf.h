@@ -58,8 +58,17 @@ typedef enum { NMF_X_F32 = 0, NMF_X_BF16 = 1, NMF_X_F16 = 2 } nmf_xdtype;
  * still lie in range). A coordinate with a zero Gram diagonal keeps its warm
  * start projected onto x >= 0; a singular passive-set system or the pivoting
  * cap of 10 r + 20 steps returns the last complete iterate projected onto
- * x >= 0. EXACT is not available to batched solves. */
-typedef enum { NMF_INNER_FIXED = 0, NMF_INNER_EXACT = 1 } nmf_inner;
+ * x >= 0. EXACT is not available to batched solves.
+ * ADAPTIVE: the inner loop of A-HALS as the cited A-HALS work sets it (the
+ * paper only says the rows are updated several times; this rule is recalled
+ * from that work): on the W side at most floor(1 + inner_alpha rho_W) sweeps,
+ * rho_W = 1 + (mn + nr) / (m (r + 1)) the cost of forming X H^T and H H^T
+ * over that of one sweep (nnz for mn with sparse X), also capped at inner_k;
+ * after each sweep l >= 2 the loop stops once ||W^(l) - W^(l-1)||_F <=
+ * inner_delta ||W^(1) - W^(0)||_F. The H side swaps m and n. Between sweeps
+ * the factor is kept in FP64. The sweeps run per iteration can be read with
+ * nmf_read_sweeps. ADAPTIVE is not available to batched solves. */
+typedef enum { NMF_INNER_FIXED = 0, NMF_INNER_EXACT = 1, NMF_INNER_ADAPTIVE = 2 } nmf_inner;
 
 /* How the two O(mnr) products X^T W and X H^T are computed. Whatever the
  * choice, the products are summed over K-chunks in FP64, and the HALS sweeps,
@@ -121,6 +130,8 @@ typedef struct {
     int32_t x_dtype;            /* nmf_xdtype                                   */
     int32_t prod;               /* nmf_prod                                     */
     int32_t flags;              /* NMF_FLAG_*                                   */
+    double inner_alpha;         /* ADAPTIVE: cost-ratio weight, >= 0 (0.5)      */
+    double inner_delta;         /* ADAPTIVE: stopping ratio, >= 0 (0.1)         */
 } nmf_params;
 
 void nmf_params_default(nmf_params *p);
@@ -197,6 +208,14 @@ enum nmf_phase {
  * Errors: NMF_E_STATE before nmf_start, NMF_E_INVAL (iters < 1, ms NULL, or
  * fewer than iters iterations left before max_iter), NMF_E_DEVICE. */
 nmf_status nmf_profile(nmf_ctx *ctx, int32_t iters, void *stream, double *ms);
+
+/* Sweeps of the inner loop run in each completed iteration: sweeps[2(k-1)]
+ * on H and sweeps[2(k-1)+1] on W for k = 1..*n_iter (inner_k for FIXED, the
+ * counts of the adaptive loop for ADAPTIVE, 0 for EXACT). sweeps may be NULL
+ * (then only *n_iter is set); cap is its length in pairs. Synchronizes the
+ * device. Errors: NMF_E_INVAL (NULL ctx, cap < *n_iter), NMF_E_STATE (no
+ * successful nmf_start), NMF_E_DEVICE. */
+nmf_status nmf_read_sweeps(nmf_ctx *ctx, int32_t *sweeps, int32_t cap, int32_t *n_iter);
 
 /* The diagnostic of section 4: for each iteration k = 1..*n_iter, the beta
  * that would have minimized ||X - (W_n + beta (W_n - W)) H_w||_F, i.e.

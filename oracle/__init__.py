@@ -19,6 +19,7 @@ CMP_LAST_ACCEPTED = 2
 ERR_REMARK1 = 4
 ROUND_F32 = 8
 EXACT_NNLS = 16
+ADAPTIVE_INNER = 32
 
 _lib = None
 
@@ -34,7 +35,8 @@ class _Params(C.Structure):
                 ("gamma_bar", C.c_double), ("eta", C.c_double),
                 ("inner_k", C.c_int), ("max_iter", C.c_int),
                 ("tol", C.c_double), ("flags", C.c_int),
-                ("replay", C.c_void_p)]
+                ("replay", C.c_void_p), ("inner_alpha", C.c_double),
+                ("inner_delta", C.c_double), ("sweeps_replay", C.c_void_p)]
 
 
 def lib():
@@ -44,7 +46,7 @@ def lib():
             build()
         _lib = C.CDLL(LIB)
         d, i, p = C.c_double, C.c_int, C.c_void_p
-        _lib.oracle_eahals.argtypes = [p, i, p, p, p, p, p, p, p, p, p, p, p]
+        _lib.oracle_eahals.argtypes = [p, i, p, p, p, p, p, p, p, p, p, p, p, p, p]
         _lib.oracle_eahals.restype = i
         _lib.oracle_nnls_h.argtypes = [p, i, p, p, i]
         _lib.oracle_nnls_w.argtypes = [p, i, p, p, i]
@@ -83,10 +85,13 @@ class _Held:
 
 
 def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
-          eta=1.5, inner_k=10, max_iter=100, tol=0.0, flags=0, replay=None):
+          eta=1.5, inner_k=10, max_iter=100, tol=0.0, flags=0, replay=None,
+          inner_alpha=0.5, inner_delta=0.1, sweeps_replay=None):
     """Run Alg. 2 with Alg. 3 and return a dict with W, H (last accepted),
     trace (rho(0..n_iter)), accepted, beta, margin, beta_star (section 4,
-    per iteration) and n_iter."""
+    per iteration), sweeps (HALS sweeps on H and on W per iteration),
+    sweep_margin (closest call of each adaptive stop decision) and n_iter.
+    sweeps_replay forces the adaptive sweep counts ((max_iter, 2) array)."""
     h = _Held(X)
     W0 = np.ascontiguousarray(W0, dtype=np.float64).reshape(h.m, r)
     H0 = np.ascontiguousarray(H0, dtype=np.float64).reshape(r, h.n)
@@ -97,22 +102,32 @@ def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
     beta = np.zeros(max(max_iter, 1))
     margin = np.zeros(max(max_iter, 1))
     bstar = np.zeros(max(max_iter, 1))
+    sweeps = np.zeros((max(max_iter, 1), 2), dtype=np.int32)
+    smargin = np.zeros((max(max_iter, 1), 2))
+    sr = None
+    if sweeps_replay is not None:
+        sr = np.ascontiguousarray(sweeps_replay, dtype=np.int32).reshape(-1, 2)
+        if sr.shape[0] < max_iter:
+            raise ValueError("sweeps_replay needs max_iter rows")
     rp = None
     if replay is not None:
         rp = np.ascontiguousarray(replay, dtype=np.uint8)
         if rp.size < max_iter:
             raise ValueError("replay needs max_iter decisions")
     prm = _Params(hp, beta0, gamma, gamma_bar, eta, inner_k, max_iter, tol,
-                  flags, None if rp is None else _ptr(rp).value)
+                  flags, None if rp is None else _ptr(rp).value, inner_alpha, inner_delta,
+                  None if sr is None else _ptr(sr).value)
     nit = C.c_int(0)
     st = lib().oracle_eahals(C.byref(h.s), r, _ptr(W0), _ptr(H0), C.byref(prm),
                              _ptr(W), _ptr(H), _ptr(trace), _ptr(acc),
-                             _ptr(beta), _ptr(margin), C.byref(nit), _ptr(bstar))
+                             _ptr(beta), _ptr(margin), C.byref(nit), _ptr(bstar),
+                             _ptr(sweeps), _ptr(smargin))
     if st != OK:
         raise RuntimeError(f"oracle_eahals failed with status {st}")
     k = nit.value
     return dict(W=W, H=H, trace=trace[:k + 1], accepted=acc[:k].astype(bool),
-                beta=beta[:k], margin=margin[:k], beta_star=bstar[:k], n_iter=k)
+                beta=beta[:k], margin=margin[:k], beta_star=bstar[:k], sweeps=sweeps[:k],
+                sweep_margin=smargin[:k], n_iter=k)
 
 
 def beta_star(X, Wn, W, Hw):

@@ -421,15 +421,69 @@ static void extrapolate(int64_t len, double beta, const double *N,
     }
 }
 
+/* --------------------------------------------- adaptive inner loop (R18) */
+
+/* Sweep cap of one side: floor(1 + alpha rho), rho = 1 + (mn + K r) / (R (r + 1)),
+ * R the rows of the factor being updated and K the rows of the fixed one,
+ * capped at inner_k and at least 1. */
+static int inner_cap(const oracle_matrix *X, int r, int w_side, const oracle_params *p)
+{
+    const double m = (double)X->m, n = (double)X->n;
+    const double mn = X->dense ? m * n : (double)X->row_ptr[X->m];
+    const double rho = w_side ? 1.0 + (mn + n * r) / (m * (r + 1.0))
+                              : 1.0 + (mn + m * r) / (n * (r + 1.0));
+    double cap = floor(1.0 + p->inner_alpha * rho);
+    if (cap > p->inner_k) cap = p->inner_k;
+    return cap < 1.0 ? 1 : (int)cap;
+}
+
+static double change_norm(int64_t len, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < len; ++i) s += (a[i] - b[i]) * (a[i] - b[i]);
+    return sqrt(s);
+}
+
+/* HALS sweeps on one side until the cap or the stopping ratio; returns the
+ * number of sweeps run. `sweep` applies one sweep to x (len entries).
+ * forced > 0 replays that count instead of deciding; *margin receives the
+ * closest call among the stopping tests made, min |d_l / (delta d_1) - 1|
+ * (infinity when none was made or delta d_1 = 0). */
+static int adaptive_sweeps(int64_t len, double *x, double *prev, int cap, double delta,
+                           void (*sweep)(int64_t, int, const double *, const double *, double *),
+                           int64_t rows, int r, const double *lin, const double *gram,
+                           int forced, double *margin)
+{
+    double eps0 = 0.0;
+    *margin = INFINITY;
+    if (forced > 0) cap = forced;
+    int l;
+    for (l = 1; l <= cap; ++l) {
+        memcpy(prev, x, sizeof(double) * len);
+        sweep(rows, r, lin, gram, x);
+        const double d = change_norm(len, x, prev);
+        if (l == 1) {
+            eps0 = d;
+            continue;
+        }
+        const double bound = delta * eps0;
+        if (bound > 0.0 && fabs(d / bound - 1.0) < *margin) *margin = fabs(d / bound - 1.0);
+        if (forced > 0 ? l == forced : d <= bound) break;
+    }
+    return l > cap ? cap : l;
+}
+
 int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
                   const double *H0, const oracle_params *p, double *W,
                   double *H, double *trace, uint8_t *accepted,
                   double *beta_used, double *margin, int *n_iter,
-                  double *beta_star)
+                  double *beta_star, int *sweeps, double *sweep_margin)
 {
     if (!valid_matrix(X) || r < 1 || p == NULL || p->hp < 1 || p->hp > 3 ||
         p->max_iter < 0 || p->inner_k < 1)
         return ORACLE_EINVAL;
+    const int adaptive = (p->flags & ORACLE_ADAPTIVE_INNER) != 0;
+    if (adaptive && !(p->inner_alpha >= 0.0 && p->inner_delta >= 0.0)) return ORACLE_EINVAL;
     const int64_t m = X->m, n = X->n;
     const int64_t mr = m * r, rn = (int64_t)r * n;
     const double nx2 = frob2(X);
@@ -442,8 +496,9 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
     double *Hyn = malloc(sizeof(double) * rn), *C = malloc(sizeof(double) * rn);
     double *G = malloc(sizeof(double) * r * r), *B = malloc(sizeof(double) * r * r);
     double *work = malloc(sizeof(double) * (r * r + r));
+    double *prev = malloc(sizeof(double) * (mr > rn ? mr : rn));
     int status = ORACLE_OK;
-    if (!Wy || !Wn || !Wyn || !A || !Hy || !Hn || !Hyn || !C || !G || !B || !work) {
+    if (!Wy || !Wn || !Wyn || !A || !Hy || !Hn || !Hyn || !C || !G || !B || !work || !prev) {
         status = ORACLE_ENOMEM;
         goto done;
     }
@@ -475,8 +530,14 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         wt_x(X, r, Wy, C);
         gram_cols(m, r, Wy, G);
         memcpy(Hn, Hy, sizeof(double) * rn);
+        int sw_h = 0, sw_w = 0;
+        double mg_h = INFINITY, mg_w = INFINITY;
         if (p->flags & ORACLE_EXACT_NNLS) exact_rows_h(n, r, C, G, Hn, work);
-        else for (int s = 0; s < p->inner_k; ++s) hals_rows_h(n, r, C, G, Hn);
+        else if (adaptive)
+            sw_h = adaptive_sweeps(rn, Hn, prev, inner_cap(X, r, 0, p), p->inner_delta,
+                                   hals_rows_h, n, r, C, G,
+                                   p->sweeps_replay ? p->sweeps_replay[2 * (k - 1)] : 0, &mg_h);
+        else for (sw_h = 0; sw_h < p->inner_k; ++sw_h) hals_rows_h(n, r, C, G, Hn);
         round_f32(rn, Hn, p->flags);
 
         /* hp >= 2: extrapolate H now (hp = 3: and project). R6: for hp = 1
@@ -491,7 +552,19 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         gram_rows(n, r, Hw, B);
         memcpy(Wn, Wy, sizeof(double) * mr);
         if (p->flags & ORACLE_EXACT_NNLS) exact_cols_w(m, r, A, B, Wn, work);
-        else for (int s = 0; s < p->inner_k; ++s) hals_cols_w(m, r, A, B, Wn);
+        else if (adaptive)
+            sw_w = adaptive_sweeps(mr, Wn, prev, inner_cap(X, r, 1, p), p->inner_delta,
+                                   hals_cols_w, m, r, A, B,
+                                   p->sweeps_replay ? p->sweeps_replay[2 * (k - 1) + 1] : 0, &mg_w);
+        else for (sw_w = 0; sw_w < p->inner_k; ++sw_w) hals_cols_w(m, r, A, B, Wn);
+        if (sweeps) {
+            sweeps[2 * (k - 1)] = sw_h;
+            sweeps[2 * (k - 1) + 1] = sw_w;
+        }
+        if (sweep_margin) {
+            sweep_margin[2 * (k - 1)] = mg_h;
+            sweep_margin[2 * (k - 1) + 1] = mg_w;
+        }
         round_f32(mr, Wn, p->flags);
         if (beta_star) beta_star[k - 1] = beta_star_of(m, r, A, B, Wn, W);
 
@@ -537,7 +610,7 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
 done:
     free(Wy); free(Wn); free(Wyn); free(A);
     free(Hy); free(Hn); free(Hyn); free(C);
-    free(G); free(B); free(work);
+    free(G); free(B); free(work); free(prev);
     return status;
 }
 

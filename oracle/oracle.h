@@ -44,6 +44,13 @@
  *       not enter the objective and keeps max(0, warm start), as in R10. A
  *       singular passive-set system or the pivoting step cap (10 r + 20)
  *       ends the solve with the last complete iterate projected onto x >= 0.
+ *   R18 Adaptive inner loop (the A-HALS rule the paper cites for "several
+ *       times", not stated in the paper itself; parity unpinned against
+ *       the paper): on the W side at most floor(1 + alpha rho_W) sweeps,
+ *       rho_W = 1 + (mn + nr) / (m (r + 1)) (the cost of forming X H^T and
+ *       H H^T over that of one sweep), capped at inner_k; stop after sweep
+ *       l >= 2 once ||W^(l) - W^(l-1)||_F <= delta ||W^(1) - W^(0)||_F. The H
+ *       side swaps m and n. Sparse X uses nnz for mn.
  *   R16 The diagnostic beta* of section 4 (the beta minimizing
  *       ||X - (W_n + beta (W_n - W)) H_w||_F) is 0 when (W_n - W) H_w = 0.
  */
@@ -67,6 +74,8 @@ extern "C" {
 #define ORACLE_ROUND_F32             8  /* round the stored iterates W_n, H_n, W_y, H_y
                                            to FP32 after each update (conditioning
                                            probe; all arithmetic stays FP64)       */
+#define ORACLE_ADAPTIVE_INNER       32  /* adaptive A-HALS inner loop (R18) instead of
+                                           inner_k sweeps                          */
 #define ORACLE_EXACT_NNLS           16  /* E-ANLS: solve each NNLS block exactly
                                            (block principal pivoting) instead of
                                            inner_k HALS sweeps                     */
@@ -88,9 +97,17 @@ typedef struct {
     int    flags;             /* ORACLE_* flags above                     */
     const uint8_t *replay;    /* NULL, or max_iter forced decisions
                                  (1 accept, 0 restart): decision replay   */
+    double inner_alpha;       /* R18 (ORACLE_ADAPTIVE_INNER): cost-ratio    */
+    double inner_delta;       /*   weight alpha and stopping ratio delta    */
+    const int *sweeps_replay; /* NULL, or 2 max_iter forced sweep counts
+                                 (H, W per iteration) for the adaptive loop */
 } oracle_params;
 
 /* Full solve (Alg. 2 with Alg. 3). Outputs, all caller-allocated:
+ *   sweeps[2(k-1)], sweeps[2(k-1)+1]: HALS sweeps run on H and on W in
+ *   iteration k (inner_k, the adaptive count of R18, or 0 for E-ANLS), and
+ *   sweep_margin[.]: the closest call of that side's stopping tests,
+ *   min |d_l / (delta d_1) - 1| (infinity when none was made);
  *   W (m*r), H (r*n): last accepted iterate;
  *   trace[0..n_iter]: rho(k) = e(k)/||X||_F (capacity max_iter+1);
  *   accepted[k-1], beta_used[k-1], margin[k-1] for k = 1..n_iter, where
@@ -102,7 +119,7 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
                   const double *H0, const oracle_params *p, double *W,
                   double *H, double *trace, uint8_t *accepted,
                   double *beta_used, double *margin, int *n_iter,
-                  double *beta_star);
+                  double *beta_star, int *sweeps, double *sweep_margin);
 
 /* Section 4: beta* = argmin_beta ||X - (Wn + beta (Wn - W)) Hw||_F^2 =
  * <X Hw^T - Wn Hw Hw^T, Wn - W> / <(Wn - W)^T (Wn - W), Hw Hw^T> (R16: 0 when

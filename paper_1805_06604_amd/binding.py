@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libnmf.so")
 
 EXPORTS = ("nmf_params_default", "nmf_create", "nmf_solve", "nmf_start",
            "nmf_iterate", "nmf_read", "nmf_profile", "nmf_destroy",
-           "nmf_last_error", "nmf_read_beta_star", "nmf_batch_create", "nmf_batch_submit", "nmf_batch_step",
+           "nmf_last_error", "nmf_read_beta_star", "nmf_read_sweeps", "nmf_batch_create", "nmf_batch_submit", "nmf_batch_step",
            "nmf_batch_result", "nmf_batch_destroy")
 
 
@@ -48,6 +48,7 @@ class XDtype(enum.IntEnum):
 class Inner(enum.IntEnum):
     FIXED = 0      # inner_k HALS sweeps per block (E-A-HALS)
     EXACT = 1      # exact NNLS per row by block principal pivoting (E-ANLS)
+    ADAPTIVE = 2   # A-HALS inner loop with the cost-ratio cap and early stop
 
 
 class Prod(enum.IntEnum):
@@ -85,7 +86,8 @@ class Params(C.Structure):
                 ("eta", C.c_double), ("inner_rule", C.c_int32),
                 ("inner_k", C.c_int32), ("max_iter", C.c_int32),
                 ("tol", C.c_double), ("x_dtype", C.c_int32),
-                ("prod", C.c_int32), ("flags", C.c_int32)]
+                ("prod", C.c_int32), ("flags", C.c_int32),
+                ("inner_alpha", C.c_double), ("inner_delta", C.c_double)]
 
 
 _lib = None
@@ -127,6 +129,8 @@ def lib():
         L.nmf_last_error.restype = C.c_char_p
         L.nmf_read_beta_star.argtypes = [p, p, i32, p]
         L.nmf_read_beta_star.restype = i32
+        L.nmf_read_sweeps.argtypes = [p, p, i32, p]
+        L.nmf_read_sweeps.restype = i32
         L.nmf_batch_create.argtypes = [p, p]
         L.nmf_batch_create.restype = i32
         L.nmf_batch_submit.argtypes = [p, p, p, p, p, p]
@@ -280,6 +284,15 @@ class Solver:
         out = np.zeros(cap)
         nit = C.c_int32()
         self._check(lib().nmf_read_beta_star(self._ctx, _ptr(out), cap, C.byref(nit)))
+        return out[:nit.value]
+
+    def read_sweeps(self):
+        """nmf_read_sweeps: HALS sweeps run on H and on W in each completed
+        iteration, as an (n_iter, 2) array."""
+        cap = max(self.params.max_iter, 1)
+        out = np.zeros((cap, 2), dtype=np.int32)
+        nit = C.c_int32()
+        self._check(lib().nmf_read_sweeps(self._ctx, _ptr(out), cap, C.byref(nit)))
         return out[:nit.value]
 
     def read(self, W=None, H=None, stream=None) -> Result:

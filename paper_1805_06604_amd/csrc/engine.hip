@@ -39,6 +39,7 @@ struct nmf_ctx {
     hipGraphExec_t exec = nullptr;
     bool started = false;
     int32_t launched = 0;
+    int cap_h = 0, cap_w = 0;    // adaptive inner loop: sweep caps of the two sides
     DevState hs{};       // host copy of the device state
     std::string err;
 };
@@ -121,8 +122,14 @@ nmf_status check_params(const nmf_params *p)
         return fail(nullptr, NMF_E_INVAL,
                     "need 1 < gamma_bar < gamma < eta (got %g, %g, %g)", p->gamma_bar,
                     p->gamma, p->eta);
-    if (p->inner_rule != NMF_INNER_FIXED && p->inner_rule != NMF_INNER_EXACT)
+    if (p->inner_rule != NMF_INNER_FIXED && p->inner_rule != NMF_INNER_EXACT &&
+        p->inner_rule != NMF_INNER_ADAPTIVE)
         return fail(nullptr, NMF_E_UNSUPPORTED, "inner_rule %d is not provided", p->inner_rule);
+    if (p->inner_rule == NMF_INNER_ADAPTIVE &&
+        !(p->inner_alpha >= 0.0 && std::isfinite(p->inner_alpha) && p->inner_delta >= 0.0 &&
+          std::isfinite(p->inner_delta)))
+        return fail(nullptr, NMF_E_INVAL, "inner_alpha = %g and inner_delta = %g must be finite and >= 0",
+                    p->inner_alpha, p->inner_delta);
     if (p->inner_k < 1 || p->inner_k > 1000)
         return fail(nullptr, NMF_E_INVAL, "inner_k = %d must lie in 1..1000", p->inner_k);
     if (p->max_iter < 0 || p->max_iter > (1 << 28))
@@ -189,7 +196,8 @@ void free_all(nmf_ctx *c)
         if (p) (void)hipFree(p);
     void *ptrs[] = {c->X, c->Xt, c->zexp_x, c->zexp_xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH,
                     c->b.A, c->b.Ct, c->b.part_g, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
-                    c->b.accepted, c->b.beta_used, c->b.beta_star, c->b.stage, c->b.fsl, c->b.texp};
+                    c->b.accepted, c->b.beta_used, c->b.beta_star, c->b.stage, c->b.fsl, c->b.texp,
+                    c->b.x64, c->b.part_n, c->b.sweeps};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -231,6 +239,12 @@ nmf_status alloc_buffers(nmf_ctx *c)
     HIP_TRY(c, dalloc(&b.beta_star, (size_t)c->p.max_iter + 1));
     HIP_TRY(c, hipMemsetAsync(b.beta_star, 0, sizeof(double) * (c->p.max_iter + 1), c->own));
     HIP_TRY(c, dalloc(&b.stage, (size_t)(m + n) * c->r));
+    if (c->p.inner_rule == NMF_INNER_ADAPTIVE) {
+        HIP_TRY(c, dalloc(&b.x64, (size_t)std::max(m, n) * rp));
+        HIP_TRY(c, dalloc(&b.part_n, (size_t)nblk));
+        HIP_TRY(c, dalloc(&b.sweeps, (size_t)2 * std::max(c->p.max_iter, 1)));
+        HIP_TRY(c, hipMemsetAsync(b.sweeps, 0, sizeof(int32_t) * 2 * std::max(c->p.max_iter, 1), c->own));
+    }
     if (c->prod_kernel == nmf::PK_MFMA_I8) {
         // Both products slice their factor into one shared buffer (they run in
         // stream order): (ld / 64) tiles of 4 slices x RP columns x 64 rows.
@@ -387,6 +401,7 @@ nmf_status enqueue_iteration(nmf_ctx *c, hipStream_t s, hipEvent_t *ev = nullptr
 {
     const int rp = c->rp, xd = c->p.x_dtype, pk = c->prod_kernel;
     const bool exact = c->p.inner_rule == NMF_INNER_EXACT;
+    const bool adaptive = c->p.inner_rule == NMF_INNER_ADAPTIVE;
     Buffers &b = c->b;
     auto e = [&](int i) { return ev ? ev[i] : nullptr; };
     // a1: C^T = X^T W_y ; a2-a4: H sweeps + epilogue ; a5: A = X H_w^T ;
@@ -394,11 +409,19 @@ nmf_status enqueue_iteration(nmf_ctx *c, hipStream_t s, hipEvent_t *ev = nullptr
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SLICE_W], s));
     HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pc, s, e(NMF_PHASE_PROD_CT)));
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SWEEP_H], s));
-    HIP_TRY(c, nmf::launch_sweep_h(rp, c->n, c->r, c->p.inner_k, exact, b, s, e(NMF_PHASE_FINISH_H)));
+    if (adaptive)
+        HIP_TRY(c, nmf::launch_sweep_h_adaptive(rp, c->n, c->r, c->cap_h, c->p.inner_delta, b, s,
+                                                e(NMF_PHASE_FINISH_H)));
+    else
+        HIP_TRY(c, nmf::launch_sweep_h(rp, c->n, c->r, c->p.inner_k, exact, b, s, e(NMF_PHASE_FINISH_H)));
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SLICE_H], s));
     HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pa, s, e(NMF_PHASE_PROD_A)));
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SWEEP_W], s));
-    HIP_TRY(c, nmf::launch_sweep_w(rp, c->m, c->r, c->p.inner_k, exact, b, s, e(NMF_PHASE_FINISH_W)));
+    if (adaptive)
+        HIP_TRY(c, nmf::launch_sweep_w_adaptive(rp, c->m, c->r, c->cap_w, c->p.inner_delta, b, s,
+                                                e(NMF_PHASE_FINISH_W)));
+    else
+        HIP_TRY(c, nmf::launch_sweep_w(rp, c->m, c->r, c->p.inner_k, exact, b, s, e(NMF_PHASE_FINISH_W)));
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_COUNT], s));
     return NMF_OK;
 }
@@ -455,6 +478,8 @@ void nmf_params_default(nmf_params *p)
     p->x_dtype = NMF_X_F32;
     p->prod = NMF_PROD_AUTO;
     p->flags = 0;
+    p->inner_alpha = 0.5;
+    p->inner_delta = 0.1;
 }
 
 nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
@@ -486,6 +511,18 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
     plan_product(c->pc, c->prod_kernel, c->n, c->b.n_pad, c->m, c->ldxt);
     c->b.nsplit_a = c->pa.nsplit;
     c->b.nsplit_c = c->pc.nsplit;
+    if (p->inner_rule == NMF_INNER_ADAPTIVE) {
+        // Sweep caps floor(1 + alpha rho), rho = 1 + (mn + K r) / (R (r + 1)) for
+        // R rows updated against K fixed ones (nnz for mn when X is sparse).
+        const double mn = X->fmt == NMF_CSR ? (double)X->nnz : (double)c->m * (double)c->n;
+        auto cap = [&](double rows, double fixed) {
+            const double rho = 1.0 + (mn + fixed * c->r) / (rows * (c->r + 1.0));
+            const double k = std::floor(1.0 + p->inner_alpha * rho);
+            return (int)std::max(1.0, std::min(k, (double)p->inner_k));
+        };
+        c->cap_h = cap((double)c->n, (double)c->m);
+        c->cap_w = cap((double)c->m, (double)c->n);
+    }
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -644,6 +681,27 @@ nmf_status nmf_read(nmf_ctx *c, float *W, float *H, int32_t on_device, double *t
     if (beta && k > 0)
         HIP_TRY(c, hipMemcpy(beta, c->b.beta_used, sizeof(double) * k, hipMemcpyDeviceToHost));
     if (n_iter) *n_iter = k;
+    return NMF_OK;
+}
+
+nmf_status nmf_read_sweeps(nmf_ctx *c, int32_t *sweeps, int32_t cap, int32_t *n_iter)
+{
+    if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");
+    if (!c->started) return fail(c, NMF_E_STATE, "nmf_read_sweeps before a successful nmf_start");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    DevState h{};
+    HIP_TRY(c, hipMemcpy(&h, c->b.st, sizeof(h), hipMemcpyDeviceToHost));
+    if (sweeps && cap < h.k) return fail(c, NMF_E_INVAL, "cap = %d < %d", cap, h.k);
+    if (sweeps && h.k > 0) {
+        if (c->p.inner_rule == NMF_INNER_ADAPTIVE) {
+            HIP_TRY(c, hipMemcpy(sweeps, c->b.sweeps, sizeof(int32_t) * 2 * h.k, hipMemcpyDeviceToHost));
+        } else {
+            const int32_t v = c->p.inner_rule == NMF_INNER_EXACT ? 0 : c->p.inner_k;
+            for (int32_t i = 0; i < 2 * h.k; ++i) sweeps[i] = v;
+        }
+    }
+    if (n_iter) *n_iter = h.k;
     return NMF_OK;
 }
 

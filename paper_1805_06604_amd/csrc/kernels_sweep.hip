@@ -88,6 +88,20 @@ hipError_t launch_sweep_w(int rp, int64_t m, int r, int inner_k, bool exact, con
     return hipGetLastError();
 }
 
+hipError_t launch_sweep_h_adaptive(int rp, int64_t n, int r, int cap, double delta,
+                                   const Buffers &b, hipStream_t s, hipEvent_t mid)
+{
+    NMF_RP_CALL(rp, sweep_h_adaptive, n, r, cap, delta, b, s, mid);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_w_adaptive(int rp, int64_t m, int r, int cap, double delta,
+                                   const Buffers &b, hipStream_t s, hipEvent_t mid)
+{
+    NMF_RP_CALL(rp, sweep_w_adaptive, m, r, cap, delta, b, s, mid);
+    return hipGetLastError();
+}
+
 hipError_t launch_group_sweep(int rp, bool w_side, const Group &gh, int hblocks, const Group &gf,
                               int fblocks, hipStream_t s)
 {

@@ -4,8 +4,22 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 
 namespace nmf {
+
+// f(integral_constant<int, 0>) .. f(integral_constant<int, N - 1>) in order,
+// for loops whose index must be a compile-time constant (register arrays).
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_(f, std::make_integer_sequence<int, N>{});
+}
 
 // Three buffers per factor: the accepted iterate, the NNLS output and the
 // extrapolated point. Which buffer plays which role lives in DevState, so an
@@ -39,6 +53,10 @@ struct DevState {
     double beta, betabar, beta_prev, beta_acc;
     double e_prev, e_acc, nx2, tol;
     double gamma, gamma_bar, eta, e0;
+    // Adaptive inner loop of the half-iteration in progress: ||x^(1) - x^(0)||_F,
+    // stop flag and sweeps run so far.
+    double in_eps0;
+    int32_t in_stop, in_count;
 };
 
 // Gram buffers (FP64) hold RP*RP entries, then RP inverse diagonal entries
@@ -146,6 +164,12 @@ struct Buffers {
     float *stage = nullptr;  // staging of W0 / H0 / outputs: (m + n) * r
     signed char *fsl = nullptr; // exact-integer products: the sliced factor (shared)
     int *texp = nullptr;     // and its column exponents
+    // Adaptive inner loop: the factor being updated in FP64 between its
+    // sweeps (max(m, n) x RP), the per-workgroup squared changes of a sweep,
+    // and the sweeps run per iteration (H, W).
+    double *x64 = nullptr;
+    double *part_n = nullptr;
+    int32_t *sweeps = nullptr;
 };
 
 // Last-block counters, one per kernel kind, each on its own 256-byte line.
@@ -188,6 +212,12 @@ hipError_t launch_sweep_h(int rp, int64_t n, int r, int inner_k, bool exact, con
                           hipStream_t s, hipEvent_t mid = nullptr);
 hipError_t launch_sweep_w(int rp, int64_t m, int r, int inner_k, bool exact, const Buffers &b,
                           hipStream_t s, hipEvent_t mid = nullptr);
+// The same with the adaptive inner loop: up to `cap` single sweeps, stopping
+// once a sweep changes the factor by at most delta times the first one.
+hipError_t launch_sweep_h_adaptive(int rp, int64_t n, int r, int cap, double delta,
+                                   const Buffers &b, hipStream_t s, hipEvent_t mid = nullptr);
+hipError_t launch_sweep_w_adaptive(int rp, int64_t m, int r, int cap, double delta,
+                                   const Buffers &b, hipStream_t s, hipEvent_t mid = nullptr);
 
 // Set-up of e(0): Gram of H0 (slot 0) into GH, then Gram of W0 (slot 0) into
 // GW[0] together with <W0, A>, and the initial error into the state.

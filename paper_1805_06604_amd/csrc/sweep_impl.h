@@ -57,17 +57,6 @@ __host__ __device__ constexpr int rec_len(int ngram) { return ngram * (RP * RP +
 // Solver flags read on the device (the NMF_FLAG_* values of the C ABI).
 constexpr int kFlagBetaStar = 4;
 
-template <typename F, int... I>
-__device__ __forceinline__ void static_for_(F &&f, std::integer_sequence<int, I...>)
-{
-    (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    static_for_(f, std::make_integer_sequence<int, N>{});
-}
-
 // Value of lane Q of this lane's 16-lane row.
 template <int Q>
 __device__ __forceinline__ double row_bcast(double v)
@@ -177,8 +166,16 @@ struct HalsArgs {
     int64_t gram_slot_stride;   // > 0: slot chosen by w_y (H update)
     double *part;          // per-workgroup records
     DevState *st;
-    int exact;             // sweep modes: start from the new-iterate slot, which
-                           // the exact NNLS solve has filled (used with K = 0)
+    // Sweep modes. src_mode: where x starts: 0 the extrapolated slot, 1 the
+    // new-iterate slot (filled by the exact NNLS solve, used with K = 0), 2 the
+    // FP64 buffer x64 (adaptive inner loop, epilogue with K = 0). step: 0 a
+    // whole half-iteration (K sweeps and the epilogue); 1 / 2 one sweep of the
+    // adaptive loop from the extrapolated slot / from x64, result to x64 and
+    // its squared change to part_n[block] (2: a no-op once the loop stopped).
+    int src_mode;
+    int step;
+    double *x64;
+    double *part_n;
 };
 
 // SETUP_H / SETUP_W: Gram (and for W, <W0, A>) of slot 0.
@@ -222,9 +219,11 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
         } else {
             src = st->w_y; dst_n = st->w_n; dst_y = st->w_yn; acc_slot = st->w_acc;
         }
-        if (a.exact) src = dst_n;
+        if (a.src_mode == 1) src = dst_n;
+        if (a.step == 2 && st->in_stop) return;
     }
     const float *xsrc = a.fac + src * a.slot_stride;
+    const double *x64 = (MI::sweeps && a.src_mode == 2) ? a.x64 : nullptr;
 
     // x and c in D layout: rows 4v+g of the wave's tile, coordinate 16b+lr.
     double xd[NB][4], cd[NB][4];
@@ -234,7 +233,8 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
         const bool ok = row < a.rows;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            xd[b][v] = ok ? (double)xsrc[row * RP + 16 * b + lr] : 0.0;
+            const int64_t off = row * RP + 16 * b + lr;
+            xd[b][v] = ok ? (x64 ? x64[off] : (double)xsrc[off]) : 0.0;
             double c = 0.0;
             if constexpr (MI::lin) {
                 if (ok) {
@@ -271,7 +271,10 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
             const int64_t row = row0 + lr;
             const bool ok = row < a.rows;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) xa[s] = ok ? (double)xsrc[row * RP + 4 * s + g] : 0.0;
+            for (int s = 0; s < NS; ++s) {
+                const int64_t off = row * RP + 4 * s + g;
+                xa[s] = ok ? (x64 ? x64[off] : (double)xsrc[off]) : 0.0;
+            }
         }
         __syncthreads();
         double *xs = s_buf + wave * 16 * XLD;
@@ -342,6 +345,32 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                 tn1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[4 * b + 3], s_gb[4 * b + 3][nb][lane], tn1, 0, 0, 0);
                 tcur = tn0 + tn1;
             });
+        }
+    }
+
+    // One sweep of the adaptive loop: x to the FP64 buffer, and the
+    // workgroup's squared change (each entry is read and written by the lane
+    // that owns it).
+    if constexpr (MI::sweeps) {
+        if (a.step != 0) {
+            double d2 = 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + 4 * v + g;
+                if (row < a.rows) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const int64_t off = row * RP + 16 * b + lr;
+                        const double old = (a.step == 1) ? (double)xsrc[off] : a.x64[off];
+                        const double dx = xd[b][v] - old;
+                        d2 = fma(dx, dx, d2);
+                        a.x64[off] = xd[b][v];
+                    }
+                }
+            }
+            d2 = block_sum(d2, &s_s1[0][0]);
+            if (tid == 0) a.part_n[bid] = d2;
+            return;
         }
     }
 
@@ -590,6 +619,42 @@ __device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
     if (threadIdx.x == 0) reset_counter(a.counter);
 }
 
+// Decision of the adaptive inner loop after one sweep (one workgroup): the
+// squared changes of the workgroups summed in a fixed order; the first sweep
+// sets ||x^(1) - x^(0)||_F, a later one stops the loop once its change is at
+// most delta times that. The count of sweeps run goes to sweeps[2 k + side].
+struct InnerFinArgs {
+    const double *part_n;
+    int nblk;
+    int step;              // 1 first sweep, 2 later sweep
+    int side;              // 0 H, 1 W
+    double delta;
+    DevState *st;
+    int32_t *sweeps;
+};
+
+static __global__ __launch_bounds__(256) void inner_fin_kernel(InnerFinArgs a)
+{
+    __shared__ double sh[4];
+    DevState *st = a.st;
+    if (st->done || (a.step == 2 && st->in_stop)) return;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < a.nblk; i += 256) v += a.part_n[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        const double d = sqrt(v);
+        if (a.step == 1) {
+            st->in_eps0 = d;
+            st->in_stop = 0;
+            st->in_count = 1;
+        } else {
+            st->in_count += 1;
+            if (d <= a.delta * st->in_eps0) st->in_stop = 1;
+        }
+        a.sweeps[2 * st->k + a.side] = st->in_count;
+    }
+}
+
 template <int RP, int MODE>
 __global__ __launch_bounds__(kThreads, 1) void hals_kernel(HalsArgs a)
 {
@@ -693,7 +758,7 @@ struct Launch {
             if (exact) {
                 exact_kernel<RP, MODE><<<exact_blocks(rows), kThreads, 0, s>>>(h);
                 h.K = 0;
-                h.exact = 1;
+                h.src_mode = 1;
             }
         }
         hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
@@ -713,6 +778,43 @@ struct Launch {
             hals_group_kernel<RP, SWEEP_H><<<hblocks, kThreads, 0, s>>>(gh);
             finish_group_kernel<RP, SWEEP_H><<<fblocks, 256, 0, s>>>(gf);
         }
+    }
+    // Half-iteration with the adaptive inner loop: `cap` single-sweep launches,
+    // each followed by its one-workgroup decision (launches after the stop are
+    // no-ops), then the sweep kernel with no sweeps from the FP64 buffer for
+    // the epilogue, and the finish kernel.
+    template <int MODE>
+    static void adaptive(int64_t rows, int r, int cap, double delta, const Buffers &b, bool w_side,
+                         uint32_t *counter, hipStream_t s, hipEvent_t mid)
+    {
+        constexpr int NG = ModeInfo<MODE>::ngram;
+        HalsArgs h = hals_args(RP, rows, r, 1, b, w_side);
+        h.x64 = b.x64;
+        h.part_n = b.part_n;
+        InnerFinArgs f{b.part_n, hals_blocks(rows), 1, w_side ? 1 : 0, delta, b.st, b.sweeps};
+        for (int l = 1; l <= cap; ++l) {
+            h.step = f.step = (l == 1) ? 1 : 2;
+            h.src_mode = (l == 1) ? 0 : 2;
+            hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
+            inner_fin_kernel<<<1, 256, 0, s>>>(f);
+        }
+        h.step = 0;
+        h.K = 0;
+        h.src_mode = 2;
+        hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
+        if (mid) (void)hipEventRecord(mid, s);
+        const FinArgs fa = fin_args(RP, rows, r, b, w_side, counter);
+        finish_kernel<RP, MODE><<<fin_blocks(RP, NG), 256, 0, s>>>(fa);
+    }
+    static void sweep_h_adaptive(int64_t n, int r, int cap, double delta, const Buffers &b,
+                                 hipStream_t s, hipEvent_t mid)
+    {
+        adaptive<SWEEP_H>(n, r, cap, delta, b, false, b.counters + CNT_H, s, mid);
+    }
+    static void sweep_w_adaptive(int64_t m, int r, int cap, double delta, const Buffers &b,
+                                 hipStream_t s, hipEvent_t mid)
+    {
+        adaptive<SWEEP_W>(m, r, cap, delta, b, true, b.counters + CNT_W, s, mid);
     }
     static void sweep_h(int64_t n, int r, int K, bool exact, const Buffers &b, hipStream_t s,
                         hipEvent_t mid)

@@ -559,3 +559,72 @@ def test_eanls_lowrank_beats_anls():
         ext.append(oracle.solve(p.X, 20, p.W0, p.H0, beta0=0.5, **kw)["trace"][-1])
         plain.append(oracle.solve(p.X, 20, p.W0, p.H0, beta0=0.0, **kw)["trace"][-1])
     assert np.mean(ext) < 0.1 * np.mean(plain)
+
+
+# ------------------------------------- adaptive inner loop (R18, recalled)
+
+def test_adaptive_with_zero_delta_is_fixed_at_the_cap():
+    """With delta = 0 the early stop never fires, so the adaptive loop is the
+    fixed loop at its cap: 200 x 200, r = 10 gives rho = 1 + (40000 + 2000) /
+    (200 * 11) = 20.09 and floor(1 + 0.5 rho) = 11 sweeps on either side."""
+    p = S.lowrank(0)
+    a = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=15, inner_k=50, inner_delta=0.0,
+                     flags=oracle.ADAPTIVE_INNER)
+    b = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=15, inner_k=11)
+    assert np.all(a["sweeps"] == 11)
+    np.testing.assert_array_equal(a["trace"], b["trace"])
+    np.testing.assert_array_equal(a["W"], b["W"])
+
+
+@pytest.mark.parametrize("r,inner_k,alpha,cap", [(20, 50, 0.5, 6), (20, 4, 0.5, 4),
+                                                 (10, 50, 0.0, 1), (10, 50, 1.0, 21)])
+def test_adaptive_sweep_cap(r, inner_k, alpha, cap):
+    """The cap floor(1 + alpha rho), at most inner_k: for 200 x 200, r = 20,
+    rho = 1 + 44000 / 4200 = 11.48 (cap 6 at alpha 0.5); r = 10 gives 20.09
+    (cap 21 at alpha 1, 1 at alpha 0)."""
+    p = S.fullrank(1, r=r)
+    a = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=6, inner_k=inner_k, inner_alpha=alpha,
+                     inner_delta=0.0, flags=oracle.ADAPTIVE_INNER)
+    assert np.all(a["sweeps"] == cap)
+
+
+def test_adaptive_with_huge_delta_stops_after_the_second_sweep():
+    """The stopping test applies from the second sweep on: with a delta no
+    change can exceed, every loop runs exactly two sweeps."""
+    p = S.fullrank(2)
+    a = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=10, inner_k=50, inner_delta=1e300,
+                     flags=oracle.ADAPTIVE_INNER)
+    b = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=10, inner_k=2)
+    assert np.all(a["sweeps"] == 2)
+    np.testing.assert_array_equal(a["trace"], b["trace"])
+
+
+def test_adaptive_stop_follows_the_sweep_changes():
+    """First H update of a solve: the sweep count equals the first l >= 2
+    whose change ||H^(l) - H^(l-1)||_F is at most delta ||H^(1) - H^(0)||_F,
+    from sweeps run one at a time by the pinned HALS routine."""
+    p = S.lowrank(1)
+    delta = 0.3
+    a = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=1, inner_k=50, inner_delta=delta,
+                     flags=oracle.ADAPTIVE_INNER)
+    H = p.H0.astype(np.float64)
+    d = []
+    for _ in range(11):
+        Hn = oracle.nnls_h(p.X, p.W0, H, 1)
+        d.append(np.linalg.norm(Hn - H))
+        H = Hn
+    stop = next((l for l in range(2, 12) if d[l - 1] <= delta * d[0]), 11)
+    assert 2 < stop < 11, "the case should stop strictly inside the cap"
+    assert a["sweeps"][0, 0] == stop
+
+
+def test_adaptive_replay_of_own_sweep_counts_is_identical():
+    """Forcing the adaptive loop to the counts it chose reproduces the run,
+    and the recorded closest calls are positive where a test was made."""
+    p = S.lowrank(2, r=12)
+    a = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=25, inner_k=50, flags=oracle.ADAPTIVE_INNER)
+    b = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=25, inner_k=50, flags=oracle.ADAPTIVE_INNER,
+                     sweeps_replay=a["sweeps"])
+    np.testing.assert_array_equal(a["trace"], b["trace"])
+    np.testing.assert_array_equal(a["sweeps"], b["sweeps"])
+    assert np.all(a["sweep_margin"][a["sweeps"] >= 2] > 0)
