@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--eanls-steps", type=int, default=20,
                     help="timed E-ANLS iterations on the same workload (0 disables)")
+    ap.add_argument("--adaptive-steps", type=int, default=20,
+                    help="timed E-A-HALS iterations with the adaptive inner loop (0 disables)")
+    ap.add_argument("--adaptive-cap", type=int, default=20,
+                    help="inner_k: upper bound on the adaptive loop's sweeps per side")
     return ap.parse_args()
 
 
@@ -172,6 +176,33 @@ def eanls(args, P, p, stream, torch):
                          "flops_per_iteration": flops, "ms_per_iteration": solve_ms}}
 
 
+def adaptive(args, P, p, stream, torch):
+    """E-A-HALS with the adaptive inner loop (cost-ratio cap bounded by
+    --adaptive-cap, alpha 0.5, delta 0.1) on the same resident workload."""
+    total = 5 + args.adaptive_steps
+    solver = P.Solver(p.X, args.r, hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
+                      inner_rule=P.Inner.ADAPTIVE, inner_k=args.adaptive_cap, max_iter=total)
+    solver.start(p.W0, p.H0, stream=stream)
+    solver.iterate(5, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    solver.iterate(args.adaptive_steps, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.adaptive_steps
+    sw = solver.read_sweeps()
+    res = solver.read(stream=stream)
+    solver.close()
+    timed = sw[5:]
+    return {"workload": f"planted dense {args.m}x{args.n} r={args.r}, E-A-HALS hp=3 with the adaptive "
+                        f"inner loop (alpha 0.5, delta 0.1, at most {args.adaptive_cap} sweeps)",
+            "value": 1e3 / ms, "unit": "iters/s", "ms_per_step": ms, "steps": args.adaptive_steps,
+            "mean_sweeps_h": float(timed[:, 0].mean()), "mean_sweeps_w": float(timed[:, 1].mean()),
+            "rho_final": float(res.trace[-1])}
+
+
 def serving(args, P, S):
     """Batched solves of a Poisson stream of small problems (m, n ~
     U{64..2048}, r in {5, 10, 20, 40}, X = max(0, W H + 1% noise)), each run
@@ -255,6 +286,7 @@ def main():
     pm = {"auto": P.Prod.AUTO, "valu": P.Prod.VALU, "exact": P.Prod.MFMA_EXACT,
           "fast": P.Prod.MFMA_FAST}[args.prod]
     ea = eanls(args, P, p, stream, torch) if args.eanls_steps > 0 else None
+    ad = adaptive(args, P, p, stream, torch) if args.adaptive_steps > 0 else None
     solver = P.Solver(p.X, r, hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
                       inner_k=K, max_iter=total, x_dtype=xd, prod=pm)
     del p
@@ -315,6 +347,8 @@ def main():
     }
     if ea is not None:
         out["eanls"] = ea
+    if ad is not None:
+        out["adaptive_inner"] = ad
     if args.serve_requests > 0:
         out["serving"] = serving(args, P, S)
     if args.cpu_sample > 0:
