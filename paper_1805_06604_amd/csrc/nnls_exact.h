@@ -20,6 +20,16 @@
 // skipped. Back substitution goes row by row with one broadcast per step.
 // G sits in LDS, shared by the four waves of a workgroup.
 //
+// Nearly full passive sets take a shorter exact route. With z = G^-1 c (once
+// per row) and N the q coordinates off the passive set, the solution with
+// x_N = 0 is x = z - G^-1(:,N) l with (G^-1)_NN l = z_N, and the dual
+// variables on N are y_N = -l (those on the passive set are zero): a q x q
+// solve and a rank-q correction per step instead of the elimination. Each
+// workgroup inverts G once in LDS (in-place Gauss-Jordan on the coordinates
+// with a positive diagonal); a pivot that shrinks below 1e-10 of its diagonal
+// sends every row to the elimination. A step takes this route when q <=
+// kQFast in every segment of the wave.
+//
 // A coordinate with a zero Gram diagonal does not enter the objective and
 // keeps max(0, warm start); a singular passive-set system (a pivot <= 0) or
 // the step cap 10 r + 20 ends the solve with the last complete iterate,
@@ -30,6 +40,8 @@
 
 namespace nmf {
 namespace sweep {
+
+constexpr int kQFast = 8;
 
 template <int RP>
 struct ExactShape {
@@ -48,6 +60,10 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
     __shared__ double s_b[kWaves][64];
     __shared__ double s_x[kWaves][64];
     __shared__ double s_d[kWaves][64];
+    __shared__ double s_ginv[RP * RP];
+    __shared__ double s_z[kWaves][64];
+    __shared__ double s_rowp[RP], s_colp[RP];
+    __shared__ int s_ginv_ok;
 
     DevState *st = a.st;
     if (st->done) return;
@@ -62,6 +78,43 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
     for (int e = threadIdx.x; e < RP * RP; e += kThreads) s_g[e] = G[e];
     __syncthreads();
 
+    // G^-1 on the coordinates with a positive diagonal (zero elsewhere), by
+    // in-place Gauss-Jordan: pivot p maps a = A(p,p) to 1/a, row p to A(p,j)/a,
+    // column p to -A(i,p)/a and the rest to A(i,j) - A(i,p) A(p,j)/a.
+    auto posc = [&](int i) { return i < a.r && s_g[i * RP + i] > 0.0; };
+    for (int e = threadIdx.x; e < RP * RP; e += kThreads) {
+        const int i = e / RP, j = e % RP;
+        s_ginv[e] = (posc(i) && posc(j)) ? s_g[e] : 0.0;
+    }
+    if (threadIdx.x == 0) s_ginv_ok = 1;
+    __syncthreads();
+    for (int p = 0; p < RP; ++p) {
+        if (!posc(p)) continue;
+        const double piv = s_ginv[p * RP + p];
+        if (!(piv > 1e-10 * s_g[p * RP + p])) {
+            if (threadIdx.x == 0) s_ginv_ok = 0;
+            break;
+        }
+        const double inv = 1.0 / piv;
+        if (threadIdx.x < RP) {
+            s_rowp[threadIdx.x] = s_ginv[p * RP + threadIdx.x];
+            s_colp[threadIdx.x] = s_ginv[threadIdx.x * RP + p];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < RP * RP; e += kThreads) {
+            const int i = e / RP, j = e % RP;
+            double v;
+            if (i == p && j == p) v = inv;
+            else if (i == p) v = s_rowp[j] * inv;
+            else if (j == p) v = -s_colp[i] * inv;
+            else v = s_ginv[e] - s_colp[i] * s_rowp[j] * inv;
+            s_ginv[e] = v;
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    const bool ginv_ok = s_ginv_ok != 0;
+
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int seg = lane / SEG, k = lane % SEG, sb = seg * SEG;
     const int kk = k < RP ? k : RP - 1;          // LDS column of idle lanes (RP = 48)
@@ -70,6 +123,7 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
     const float *xsrc = a.fac + src * a.slot_stride;
     float *xdst = a.fac + dst * a.slot_stride;
     double *col = s_col[wave], *bb = s_b[wave], *xs = s_x[wave], *sd = s_d[wave];
+    double *zs = s_z[wave];
 
     for (int pass = 0; pass < PASSES; ++pass) {
         const int64_t row = (int64_t)bid * kExactRows + (pass * kWaves + wave) * NSEG + seg;
@@ -82,6 +136,20 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
             w = (double)xsrc[row * RP + k];
         }
         const bool pos = valid && k < a.r && s_g[kk * RP + kk] > 0.0;
+        const uint64_t pm = (__ballot(pos) >> sb) & segmask;    // coordinates that enter
+        // z = G^-1 c (fast route).
+        if (ginv_ok) {
+            xs[lane] = c;
+            __builtin_amdgcn_wave_barrier();
+            double z = 0.0;
+            static_for<RP>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                z = fma(s_ginv[j * RP + kk], xs[sb + j], z);
+            });
+            __builtin_amdgcn_wave_barrier();
+            zs[lane] = z;
+            __builtin_amdgcn_wave_barrier();
+        }
         const double x0 = fmax(w, 0.0);
         double x = x0;                           // last complete iterate
         bool F = pos && w > 0.0;                 // passive set
@@ -100,68 +168,124 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
 #pragma unroll
             for (int q = 0; q < NSEG; ++q) fu |= (fw >> (q * SEG)) & segmask;
 
-            // Row k of the system: G restricted to the passive set (rows and
-            // columns off it are zero; their pivots are skipped and their
-            // solution is 0).
-            double M[RP];
-            static_for<RP>([&](auto J) {
-                constexpr int j = decltype(J)::value;
-                const double gj = s_g[j * RP + kk];
-                M[j] = (F && ((fm >> j) & 1)) ? gj : 0.0;
-            });
-            double b = F ? c : 0.0;
+            const uint64_t nm = pm & ~fm;                  // off the passive set
+            const int q = __popcll(nm);
+            const bool fast = ginv_ok && __ballot(!done && q > kQFast) == 0;
+            double xn, y = 0.0;
             bool fail = false;
-
-            // Elimination: rows k > p lose f_k times row p, f_k = S(k,p) / S(p,p);
-            // row p of the trailing matrix is column p by symmetry.
-            static_for<RP>([&](auto P) {
-                constexpr int p = decltype(P)::value;
-                if ((fu >> p) & 1) {
-                    col[lane] = M[p];
-                    bb[lane] = b;
-                    __builtin_amdgcn_wave_barrier();
-                    const double d = col[sb + p], bp = bb[sb + p];
-                    const bool pp = (fm >> p) & 1;
-                    const bool ok = d > 0.0;
-                    if (pp && !ok) fail = true;
-                    const double f = (pp && ok && kl > p) ? M[p] / d : 0.0;
-                    sd[sb + p] = d;
-                    static_for<RP - p - 1>([&](auto J) {
-                        constexpr int j = p + 1 + decltype(J)::value;
-                        M[j] = fma(-f, col[sb + j], M[j]);
-                    });
-                    b = fma(-f, bp, b);
-                    __builtin_amdgcn_wave_barrier();
+            if (fast) {
+                // The q <= kQFast coordinates of N in order, (G^-1)_NN and z_N
+                // (the same in every lane of the segment).
+                int ni[kQFast];
+                uint64_t t = nm;
+#pragma unroll
+                for (int u = 0; u < kQFast; ++u) {
+                    ni[u] = t ? __builtin_ctzll(t) : 0;
+                    t &= t - 1;
                 }
-            });
-
-            // Back substitution: x_p = (b_p - sum_{j > p} S(p,j) x_j) / S(p,p),
-            // the sum accumulated in lane p as the later x_j become known; a
-            // lane's value is final once its own step is done.
-            const double rdk = F ? 1.0 / sd[sb + kk] : 1.0;
-            double acc = 0.0;
-            static_for<RP>([&](auto P) {
-                constexpr int p = RP - 1 - decltype(P)::value;
-                if ((fu >> p) & 1) {
-                    xs[lane] = (b - acc) * rdk;
-                    __builtin_amdgcn_wave_barrier();
-                    const double xp = xs[sb + p];
-                    acc = fma(kl < p ? M[p] : 0.0, xp, acc);
-                    __builtin_amdgcn_wave_barrier();
+                double S[kQFast][kQFast], lz[kQFast];
+#pragma unroll
+                for (int u = 0; u < kQFast; ++u) {
+                    lz[u] = u < q ? zs[sb + ni[u]] : 0.0;
+#pragma unroll
+                    for (int v = 0; v < kQFast; ++v)
+                        S[u][v] = (u < q && v < q) ? s_ginv[ni[u] * RP + ni[v]] : (u == v ? 1.0 : 0.0);
                 }
-            });
-            const double sol = (b - acc) * rdk;
-            const double xn = pos ? (F ? sol : 0.0) : x0;
+                // (G^-1)_NN l = z_N by symmetric elimination and back substitution.
+#pragma unroll
+                for (int pp = 0; pp < kQFast; ++pp) {
+                    if (pp < q && !(S[pp][pp] > 0.0)) fail = true;
+                    const double inv = 1.0 / S[pp][pp];
+#pragma unroll
+                    for (int i = pp + 1; i < kQFast; ++i) {
+                        const double f = S[i][pp] * inv;
+#pragma unroll
+                        for (int j = pp + 1; j < kQFast; ++j) S[i][j] = fma(-f, S[pp][j], S[i][j]);
+                        lz[i] = fma(-f, lz[pp], lz[i]);
+                    }
+                }
+#pragma unroll
+                for (int pp = kQFast - 1; pp >= 0; --pp) {
+                    double v = lz[pp];
+#pragma unroll
+                    for (int j = pp + 1; j < kQFast; ++j) v = fma(-S[pp][j], lz[j], v);
+                    lz[pp] = v / S[pp][pp];
+                }
+                // x = z - G^-1(:,N) l on the passive set; y_N = -l.
+                double xf = zs[lane];
+                int myidx = 0;
+#pragma unroll
+                for (int u = 0; u < kQFast; ++u) {
+                    if (u < q) xf = fma(-s_ginv[ni[u] * RP + kk], lz[u], xf);
+                    if (u < q && ni[u] == k) myidx = u;
+                }
+                xn = pos ? (F ? xf : 0.0) : x0;
+#pragma unroll
+                for (int u = 0; u < kQFast; ++u)
+                    if (u == myidx) y = -lz[u];
+            } else {
+                // Row k of the system: G restricted to the passive set (rows and
+                // columns off it are zero; their pivots are skipped and their
+                // solution is 0).
+                double M[RP];
+                static_for<RP>([&](auto J) {
+                    constexpr int j = decltype(J)::value;
+                    const double gj = s_g[j * RP + kk];
+                    M[j] = (F && ((fm >> j) & 1)) ? gj : 0.0;
+                });
+                double b = F ? c : 0.0;
 
-            // Dual variables y = G x - c and the infeasible coordinates.
-            xs[lane] = xn;
-            __builtin_amdgcn_wave_barrier();
-            double y = -c;
-            static_for<RP>([&](auto J) {
-                constexpr int j = decltype(J)::value;
-                y = fma(s_g[j * RP + kk], xs[sb + j], y);
-            });
-            __builtin_amdgcn_wave_barrier();
+                // Elimination: rows k > p lose f_k times row p, f_k = S(k,p) / S(p,p);
+                // row p of the trailing matrix is column p by symmetry.
+                static_for<RP>([&](auto P) {
+                    constexpr int p = decltype(P)::value;
+                    if ((fu >> p) & 1) {
+                        col[lane] = M[p];
+                        bb[lane] = b;
+                        __builtin_amdgcn_wave_barrier();
+                        const double d = col[sb + p], bp = bb[sb + p];
+                        const bool pp = (fm >> p) & 1;
+                        const bool ok = d > 0.0;
+                        if (pp && !ok) fail = true;
+                        const double f = (pp && ok && kl > p) ? M[p] / d : 0.0;
+                        sd[sb + p] = d;
+                        static_for<RP - p - 1>([&](auto J) {
+                            constexpr int j = p + 1 + decltype(J)::value;
+                            M[j] = fma(-f, col[sb + j], M[j]);
+                        });
+                        b = fma(-f, bp, b);
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                });
+
+                // Back substitution: x_p = (b_p - sum_{j > p} S(p,j) x_j) / S(p,p),
+                // the sum accumulated in lane p as the later x_j become known; a
+                // lane's value is final once its own step is done.
+                const double rdk = F ? 1.0 / sd[sb + kk] : 1.0;
+                double acc = 0.0;
+                static_for<RP>([&](auto P) {
+                    constexpr int p = RP - 1 - decltype(P)::value;
+                    if ((fu >> p) & 1) {
+                        xs[lane] = (b - acc) * rdk;
+                        __builtin_amdgcn_wave_barrier();
+                        const double xp = xs[sb + p];
+                        acc = fma(kl < p ? M[p] : 0.0, xp, acc);
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                });
+                const double sol = (b - acc) * rdk;
+                xn = pos ? (F ? sol : 0.0) : x0;
+
+                // Dual variables y = G x - c and the infeasible coordinates.
+                xs[lane] = xn;
+                __builtin_amdgcn_wave_barrier();
+                y = -c;
+                static_for<RP>([&](auto J) {
+                    constexpr int j = decltype(J)::value;
+                    y = fma(s_g[j * RP + kk], xs[sb + j], y);
+                });
+                __builtin_amdgcn_wave_barrier();
+            }
             const bool viol = pos && (F ? xn < 0.0 : y < 0.0);
             const uint64_t vm = (__ballot(viol) >> sb) & segmask;
             const int nv = __popcll(vm);
