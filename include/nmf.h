@@ -58,7 +58,7 @@ typedef enum { NMF_X_F32 = 0, NMF_X_BF16 = 1, NMF_X_F16 = 2 } nmf_xdtype;
  * still lie in range). A coordinate with a zero Gram diagonal keeps its warm
  * start projected onto x >= 0; a singular passive-set system or the pivoting
  * cap of 10 r + 20 steps returns the last complete iterate projected onto
- * x >= 0. EXACT is not available to batched solves.
+ * x >= 0.
  * ADAPTIVE: the inner loop of A-HALS as the cited A-HALS work sets it (the
  * paper only says the rows are updated several times; this rule is recalled
  * from that work): on the W side at most floor(1 + inner_alpha rho_W) sweeps,

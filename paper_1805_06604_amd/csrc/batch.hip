@@ -5,8 +5,9 @@
 // aligned blocks) with the same buffers as a single-problem context. A batch
 // iteration runs one outer iteration of Algorithm 2 for every active problem:
 // per padded rank, eight grouped launches (factor slicing, Xᵀ W_y, H sweeps,
-// H finish, factor slicing, X H_wᵀ, W sweeps, W finish), each covering the
-// blocks of all problems of that rank, so that small problems share the chip
+// H finish, factor slicing, X H_wᵀ, W sweeps, W finish), and before each
+// sweep launch the exact NNLS solves of the E-ANLS problems if there are any,
+// each covering the blocks of all problems of that rank, so that small problems share the chip
 // instead of each paying its own launch latency. A problem that stopped
 // (its device state says done) returns at the entry of every kernel until
 // the host retires it at the next completion check.
@@ -34,7 +35,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kClasses = 4;          // padded ranks 16, 32, 48, 64
-constexpr int kKinds = 8;            // grouped kernels of one iteration
+constexpr int kKinds = 10;           // grouped kernels of one iteration (8, and the
+                                     // exact NNLS solves of E-ANLS problems, H and W)
 constexpr int64_t kBatchTargetWG = 64;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -343,12 +345,19 @@ nmf_status rebuild(nmf_batch *B)
             E.pa = q.pa;
             E.hh = nmf::sweep::hals_args(rp, q.n, q.r, q.p.inner_k, q.b, false);
             E.hw = nmf::sweep::hals_args(rp, q.m, q.r, q.p.inner_k, q.b, true);
+            const bool exact = q.p.inner_rule == NMF_INNER_EXACT;
+            if (exact) {        // the exact solve fills the new slot; no sweeps after it
+                E.hh.K = E.hw.K = 0;
+                E.hh.src_mode = E.hw.src_mode = 1;
+            }
             E.fh = nmf::sweep::fin_args(rp, q.n, q.r, q.b, false, q.b.counters + nmf::CNT_H);
             E.fw = nmf::sweep::fin_args(rp, q.m, q.r, q.b, true, q.b.counters + nmf::CNT_W);
             const int nb[kKinds] = {(int)(q.pc.ld / 64), (int)(q.pc.rows_pad / 128 * q.pc.nsplit),
                                     nmf::sweep::hals_blocks(q.n), nmf::sweep::fin_blocks(rp, 1),
                                     (int)(q.pa.ld / 64), (int)(q.pa.rows_pad / 128 * q.pa.nsplit),
-                                    nmf::sweep::hals_blocks(q.m), nmf::sweep::fin_blocks(rp, 2)};
+                                    nmf::sweep::hals_blocks(q.m), nmf::sweep::fin_blocks(rp, 2),
+                                    exact ? nmf::sweep::exact_blocks(q.n) : 0,
+                                    exact ? nmf::sweep::exact_blocks(q.m) : 0};
             for (int k = 0; k < kKinds; ++k) {
                 int *P = &pre[((size_t)c * kKinds + k) * (cap + 1)];
                 P[i + 1] = P[i] + nb[k];
@@ -389,10 +398,14 @@ nmf_status run_iterations(nmf_batch *B, int iters)
             hipStream_t cs = B->cs[c];
             BHIP(nmf::i8::launch_group(rp, group_of(B, c, 0, offsetof(Entry, pc)), nb[0],
                                        group_of(B, c, 1, offsetof(Entry, pc)), nb[1], cs));
+            if (nb[8] > 0)
+                BHIP(nmf::launch_group_exact(rp, false, group_of(B, c, 8, offsetof(Entry, hh)), nb[8], cs));
             BHIP(nmf::launch_group_sweep(rp, false, group_of(B, c, 2, offsetof(Entry, hh)), nb[2],
                                          group_of(B, c, 3, offsetof(Entry, fh)), nb[3], cs));
             BHIP(nmf::i8::launch_group(rp, group_of(B, c, 4, offsetof(Entry, pa)), nb[4],
                                        group_of(B, c, 5, offsetof(Entry, pa)), nb[5], cs));
+            if (nb[9] > 0)
+                BHIP(nmf::launch_group_exact(rp, true, group_of(B, c, 9, offsetof(Entry, hw)), nb[9], cs));
             BHIP(nmf::launch_group_sweep(rp, true, group_of(B, c, 6, offsetof(Entry, hw)), nb[6],
                                          group_of(B, c, 7, offsetof(Entry, fw)), nb[7], cs));
         }
@@ -497,8 +510,8 @@ nmf_status nmf_batch_submit(nmf_batch *B, const nmf_matrix *X, const nmf_params 
         return berr(NMF_E_UNSUPPORTED, "batched solves take dense X");
     if (p->x_dtype != NMF_X_F32)
         return berr(NMF_E_UNSUPPORTED, "batched solves keep X in FP32 (exact-integer products)");
-    if (p->inner_rule != NMF_INNER_FIXED)
-        return berr(NMF_E_UNSUPPORTED, "batched solves run the fixed inner rule (A-HALS)");
+    if (p->inner_rule == NMF_INNER_ADAPTIVE)
+        return berr(NMF_E_UNSUPPORTED, "batched solves run the fixed or the exact inner rule");
     if (!W0 || !H0) return berr(NMF_E_INVAL, "W0 and H0 must not be NULL");
     const int64_t m = X->m, n = X->n;
     const int r = p->r;

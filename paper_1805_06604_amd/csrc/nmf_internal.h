@@ -257,6 +257,7 @@ namespace i8 {
 hipError_t launch_group(int rp, const Group &gs, int sblocks, const Group &gp, int pblocks,
                         hipStream_t s);
 }
+hipError_t launch_group_exact(int rp, bool w_side, const Group &g, int blocks, hipStream_t s);
 hipError_t launch_group_sweep(int rp, bool w_side, const Group &gh, int hblocks, const Group &gf,
                               int fblocks, hipStream_t s);
 

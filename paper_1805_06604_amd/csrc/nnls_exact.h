@@ -320,5 +320,16 @@ __global__ __launch_bounds__(kThreads, 2) void exact_kernel(HalsArgs a)
     exact_body<RP, MODE>(a, blockIdx.x);
 }
 
+// Grouped form: one launch over the problems of a group that solve their
+// blocks exactly (argument records and block ranges in g; the others have no
+// blocks).
+template <int RP, int MODE>
+__global__ __launch_bounds__(kThreads, 2) void exact_group_kernel(Group g)
+{
+    int lb, cnt;
+    const int p = group_find(g, blockIdx.x, &lb, &cnt);
+    exact_body<RP, MODE>(*reinterpret_cast<const HalsArgs *>(g.base + (size_t)p * g.stride), lb);
+}
+
 }  // namespace sweep
 }  // namespace nmf

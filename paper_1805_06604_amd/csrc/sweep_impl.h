@@ -691,6 +691,8 @@ __global__ __launch_bounds__(256) void finish_group_kernel(Group g)
 constexpr int kExactRows = 32;
 template <int RP, int MODE>
 __global__ __launch_bounds__(kThreads, 2) void exact_kernel(HalsArgs a);
+template <int RP, int MODE>
+__global__ __launch_bounds__(kThreads, 2) void exact_group_kernel(Group g);
 inline int exact_blocks(int64_t rows) { return (int)((rows + kExactRows - 1) / kExactRows); }
 
 // Argument records of one half-iteration (or set-up step) of one problem.
@@ -768,6 +770,12 @@ struct Launch {
     }
     // Grouped half-iteration: the sweep kernel over group gh, then the
     // finish kernel over group gf.
+    // Grouped exact NNLS solves (the problems of the group that use them).
+    static void exact_group(bool w_side, const Group &g, int blocks, hipStream_t s)
+    {
+        if (w_side) exact_group_kernel<RP, SWEEP_W><<<blocks, kThreads, 0, s>>>(g);
+        else exact_group_kernel<RP, SWEEP_H><<<blocks, kThreads, 0, s>>>(g);
+    }
     static void group(bool w_side, const Group &gh, int hblocks, const Group &gf, int fblocks,
                       hipStream_t s)
     {

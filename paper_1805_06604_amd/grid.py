@@ -1,4 +1,4 @@
-"""Batched multi-start and parameter-grid runs of E-A-HALS on one GPU.
+"""Batched multi-start and parameter-grid runs of E-A-HALS and E-ANLS on one GPU.
 
 This is the tuning protocol of arXiv 1805.06604, section 5.3. Every parameter set (β₀, η, γ, γ̄,
 hp) runs on several data sets and random initializations, and the runs are scored by the error
@@ -21,13 +21,14 @@ import json
 
 import numpy as np
 
-from .binding import Batch
+from .binding import Batch, Inner
 
-# The grid of section 5.3 for E-A-HALS on the synthetic sets, including the extra (1.005, 1.001)
-# pair tried there.
+# The grid of section 5.3 (3^4 extrapolated variants and the plain algorithm); for E-A-HALS on
+# the synthetic sets the extra (1.005, 1.001) pair tried there is included.
 BETA0 = (0.25, 0.5, 0.75)
 ETA = (1.5, 2.0, 3.0)
-GAMMAS = ((1.005, 1.001), (1.01, 1.005), (1.05, 1.01), (1.1, 1.05))
+GAMMAS_ANLS = ((1.01, 1.005), (1.05, 1.01), (1.1, 1.05))
+GAMMAS = ((1.005, 1.001),) + GAMMAS_ANLS
 HP = (1, 2, 3)
 
 
@@ -49,9 +50,10 @@ class Variant:
                     gamma_bar=self.gamma_bar)
 
     def label(self) -> str:
+        """Parameters of the variant (A-HALS / ANLS when plain)."""
         if self.plain:
-            return "A-HALS"
-        return (f"E-A-HALS hp={self.hp} beta0={self.beta0:g} eta={self.eta:g} "
+            return "plain"
+        return (f"hp={self.hp} beta0={self.beta0:g} eta={self.eta:g} "
                 f"gamma={self.gamma:g} gamma_bar={self.gamma_bar:g}")
 
 
@@ -65,17 +67,18 @@ def grid_variants(beta0=BETA0, eta=ETA, gammas=GAMMAS, hp=HP, plain=True) -> lis
 
 
 def run(problems, variants, max_iter, inner_k=10, hbm_budget=8 << 30, max_active=4096,
-        check_every=50):
+        check_every=50, inner_rule=Inner.FIXED):
     """Solves every (variant, problem) pair with max_iter outer iterations through one batch.
     Each problem carries its own X, W0 and H0, so a problem stands for one data set with one
-    initialization. Returns the Results as a list of lists, indexed [variant][problem]."""
+    initialization. inner_rule FIXED runs E-A-HALS (inner_k sweeps), EXACT runs E-ANLS.
+    Returns the Results as a list of lists, indexed [variant][problem]."""
     res = [[None] * len(problems) for _ in variants]
     with Batch(hbm_budget, max_active=max_active, check_every=check_every) as B:
         tickets = {}
         for vi, v in enumerate(variants):
             for pi, p in enumerate(problems):
                 t = B.submit(p.X, p.r, p.W0, p.H0, max_iter=max_iter, inner_k=inner_k,
-                             **v.params())
+                             inner_rule=inner_rule, **v.params())
                 tickets[t] = (vi, pi)
         while tickets:
             B.step(check_every)
@@ -124,15 +127,18 @@ def main(argv=None):
     ap.add_argument("--seeds", type=int, default=10)
     ap.add_argument("--iters", type=int, default=500)
     ap.add_argument("--r", type=int, default=20)
+    ap.add_argument("--algo", choices=["e-a-hals", "e-anls"], default="e-a-hals")
     args = ap.parse_args(argv)
     gen = S.lowrank if args.kind == "lowrank" else S.fullrank
     problems = [gen(s, r=args.r) for s in range(args.seeds)]
-    variants = grid_variants()
+    anls = args.algo == "e-anls"
+    variants = grid_variants(gammas=GAMMAS_ANLS) if anls else grid_variants()
     t0 = time.perf_counter()
-    results = run(problems, variants, args.iters)
+    results = run(problems, variants, args.iters, inner_rule=Inner.EXACT if anls else Inner.FIXED)
     dt = time.perf_counter() - t0
     summ = summarize(variants, results, e_min=[0.0] * len(problems) if args.kind == "lowrank" else None)
-    out = dict(kind=args.kind, seeds=args.seeds, iters=args.iters, runs=len(variants) * len(problems),
+    out = dict(algo=args.algo, kind=args.kind, seeds=args.seeds, iters=args.iters,
+               runs=len(variants) * len(problems),
                seconds=dt, best_worst=summ["best_worst"],
                plain=summ["rows"][0])
     print(json.dumps(out, indent=1))

@@ -98,9 +98,9 @@ def test_batch_problems_stop_independently():
     np.testing.assert_allclose(g.trace, single.trace, rtol=1e-6)
 
 
-def test_batch_rejects_the_exact_inner_rule():
+def test_batch_rejects_the_adaptive_inner_rule():
     p = _problems()[0]
     with P.Batch(1 << 24, max_active=4, check_every=1) as B:
         with pytest.raises(P.NMFError) as e:
-            B.submit(p.X, p.r, p.W0, p.H0, inner_rule=P.Inner.EXACT)
+            B.submit(p.X, p.r, p.W0, p.H0, inner_rule=P.Inner.ADAPTIVE)
     assert e.value.status == P.Status.E_UNSUPPORTED

@@ -76,3 +76,52 @@ def test_whole_grid_at_scale():
         for pi, p in enumerate(probs[:1]):
             print(v.label(), flush=True)
             compare_to_oracle(p, res[vi][pi], 30, inner_k=10, **v.params())
+
+
+def test_eanls_grid_runs_match_oracle_and_table4():
+    """E-ANLS through the batch (grouped exact NNLS solves): a sample of the
+    82-variant grid of section 5.3 matches the oracle in its exact mode, and
+    the chosen E-ANLS parameters (hp = 1, beta0 0.5, eta 1.5, gamma 1.1,
+    gamma_bar 1.05) reproduce Table 4's full-rank mean 0.423795 +- 1.161e-3
+    over 10 data sets within 3 standard errors."""
+    import oracle
+    vs = G.grid_variants(gammas=G.GAMMAS_ANLS)
+    assert len(vs) == 82
+    probs = [S.fullrank(s) for s in range(10)]
+    chosen = G.Variant(1, 0.5, 1.5, 1.1, 1.05)
+    sample = [G.PLAIN, chosen, G.Variant(3, 0.75, 2.0, 1.01, 1.005), G.Variant(2, 0.25, 3.0, 1.05, 1.01)]
+    print("E-ANLS grid: 4 variants x 10 data sets, 150 iterations", flush=True)
+    res = G.run(probs, sample, 150, inner_rule=P.Inner.EXACT)
+    for v, row in zip(sample, res):
+        for p, g in list(zip(probs, row))[:2]:
+            print(v.label(), f"seed={p.seed}", flush=True)
+            compare_to_oracle(p, g, 150, trace_iters=50, oracle_flags=oracle.EXACT_NNLS, **v.params())
+    summ = G.summarize(sample, res)
+    ext = summ["rows"][1]
+    print(ext, flush=True)
+    assert abs(ext["rho_mean"] - 0.423795) < 3 * 1.161e-3 / np.sqrt(10)
+
+
+def test_mixed_rules_in_one_batch():
+    """E-A-HALS and E-ANLS problems of the same padded rank share the grouped
+    launches; each result is that of its own rule (against the oracle)."""
+    import oracle
+    probs = [S.fullrank(s, m=180, n=150, r=12) for s in range(4)]
+    v = G.Variant(1, 0.5, 1.5, 1.1, 1.05)
+    print("mixed batch: 2 fixed + 2 exact problems, 40 iterations", flush=True)
+    out = {}
+    with P.Batch(1 << 28, max_active=8, check_every=10) as B:
+        t = [B.submit(p.X, p.r, p.W0, p.H0, max_iter=40, inner_k=10,
+                      inner_rule=P.Inner.EXACT if i % 2 else P.Inner.FIXED, **v.params())
+             for i, p in enumerate(probs)]
+        while len(out) < len(t):
+            B.step(10)
+            for i, ti in enumerate(t):
+                if i not in out:
+                    g = B.result(ti)
+                    if g is not None:
+                        out[i] = g
+    for i, p in enumerate(probs):
+        print(f"problem {i} rule {'EXACT' if i % 2 else 'FIXED'}", flush=True)
+        compare_to_oracle(p, out[i], 40, oracle_flags=oracle.EXACT_NNLS if i % 2 else 0,
+                          inner_k=10, **v.params())

@@ -5,7 +5,7 @@ from paper_1805_06604_amd import grid as G
 def test_grid_is_the_papers():
     vs = G.grid_variants()
     assert len(vs) == 1 + 3 * 3 * 3 * 4
-    assert vs[0].plain and vs[0].label() == "A-HALS"
+    assert vs[0].plain and vs[0].label() == "plain"
     assert {v.beta0 for v in vs[1:]} == {0.25, 0.5, 0.75}
     assert {v.eta for v in vs[1:]} == {1.5, 2.0, 3.0}
     assert {(v.gamma, v.gamma_bar) for v in vs[1:]} == {(1.005, 1.001), (1.01, 1.005),
