@@ -95,3 +95,23 @@ def test_fixed_rule_reports_inner_k():
     with P.Solver(p.X, p.r, max_iter=5, inner_k=7, hp=3, **ALG) as s:
         s.solve(p.W0, p.H0)
         assert np.all(s.read_sweeps() == 7)
+
+
+def test_beta_star_with_the_adaptive_loop():
+    """beta* with the adaptive loop against the oracle forced to the GPU's
+    sweep counts."""
+    p = S.lowrank(3)
+    kw = dict(hp=3, **ALG)
+    with P.Solver(p.X, p.r, max_iter=25, inner_rule=P.Inner.ADAPTIVE, inner_k=50,
+                  flags=P.FLAG_BETA_STAR, **kw) as s:
+        g = s.solve(p.W0, p.H0)
+        bs = s.read_beta_star()
+        sw = s.read_sweeps()
+    okw = dict(kw, inner_k=50, replay=g.accepted, sweeps_replay=sw)
+    ref = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=25, flags=oracle.ADAPTIVE_INNER, **okw)
+    f32 = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=25,
+                       flags=oracle.ADAPTIVE_INNER | oracle.ROUND_F32, **okw)
+    bo, bf = ref["beta_star"], f32["beta_star"]
+    tol = np.maximum(1e-6 * (1 + np.abs(bo)), 3 * np.abs(bf - bo))
+    print("beta* (adaptive)", np.round(bo[:8], 4), "max dev", np.max(np.abs(bs - bo)), flush=True)
+    assert np.all(np.abs(bs - bo) <= tol), np.max(np.abs(bs - bo) / tol)

@@ -108,3 +108,58 @@ def test_table3_eanls_beats_anls_on_low_rank():
         plain.append(_run(p, 150, hp=1, beta0=0.0, gamma=1.1, gamma_bar=1.05, eta=1.5).trace[-1])
     print(f"low-rank mean final rho: E-ANLS {np.mean(ext):.3e}, ANLS {np.mean(plain):.3e}", flush=True)
     assert np.mean(ext) < 0.1 * np.mean(plain)
+
+
+def test_rank_one():
+    """r = 1: every NNLS is one coordinate (max(0, c / g))."""
+    p = S.fullrank(9, m=90, n=70, r=1)
+    g = _run(p, 20, hp=1, **ALG)
+    _compare(p, g, 20, hp=1, **ALG)
+
+
+def test_tol_stop():
+    """The tol stop (R12) ends E-ANLS at the oracle's iteration, with the
+    oracle's trace up to there."""
+    p = S.fullrank(10, m=150, n=120, r=10)
+    g = _run(p, 200, hp=1, tol=1e-7, **ALG)
+    ref = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=200, tol=1e-7, hp=1,
+                       flags=oracle.EXACT_NNLS, **ALG)
+    assert g.n_iter == ref["n_iter"] and g.n_iter < 200
+    np.testing.assert_allclose(g.trace, ref["trace"], rtol=1e-5)
+
+
+def test_beta_star_with_exact_blocks():
+    """The beta* diagnostic of section 4 in E-ANLS, where W_n is an exact
+    NNLS solution, against the oracle in its exact mode."""
+    p = S.lowrank(0)
+    kw = dict(hp=1, **ALG)
+    with P.Solver(p.X, p.r, max_iter=30, inner_rule=P.Inner.EXACT, flags=P.FLAG_BETA_STAR, **kw) as s:
+        g = s.solve(p.W0, p.H0)
+        bs = s.read_beta_star()
+    ref = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=30, replay=g.accepted,
+                       flags=oracle.EXACT_NNLS, **kw)
+    f32 = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=30, replay=g.accepted,
+                       flags=oracle.EXACT_NNLS | oracle.ROUND_F32, **kw)
+    bo, bf = ref["beta_star"], f32["beta_star"]
+    tol = np.maximum(1e-6 * (1 + np.abs(bo)), 3 * np.abs(bf - bo))
+    print("beta* (E-ANLS)", np.round(bo[:8], 4), "max dev", np.max(np.abs(bs - bo)), flush=True)
+    assert np.all(np.abs(bs - bo) <= tol), np.max(np.abs(bs - bo) / tol)
+
+
+def test_device_pointer_interface():
+    """nmf_start / nmf_iterate / nmf_read on torch tensors give the host
+    interface's result bit for bit."""
+    torch = pytest.importorskip("torch")
+    p = S.fullrank(11, m=160, n=140, r=12)
+    kw = dict(hp=1, inner_rule=P.Inner.EXACT, **ALG)
+    with P.Solver(p.X, p.r, max_iter=15, **kw) as s:
+        a = s.solve(p.W0, p.H0)
+        st = torch.cuda.current_stream()
+        s.start(torch.from_numpy(p.W0).cuda(), torch.from_numpy(p.H0).cuda(), stream=st)
+        s.iterate(15, stream=st)
+        W = torch.empty((p.m, p.r), dtype=torch.float32, device="cuda")
+        H = torch.empty((p.r, p.n), dtype=torch.float32, device="cuda")
+        b = s.read(W, H, stream=st)
+    np.testing.assert_array_equal(a.trace, b.trace)
+    np.testing.assert_array_equal(a.W, W.cpu().numpy())
+    np.testing.assert_array_equal(a.H, H.cpu().numpy())
