@@ -183,8 +183,8 @@ class Solver:
 
     ``X`` is a float32 (m, n) numpy array, or an object with ``m, n,
     row_ptr, col_idx, val`` (CSR). Keyword arguments set nmf_params fields
-    (hp, beta0, gamma, gamma_bar, eta, inner_rule, inner_k, max_iter, tol,
-    x_dtype, prod, flags)."""
+    (hp, beta0, gamma, gamma_bar, eta, inner_rule, inner_k, inner_alpha,
+    inner_delta, max_iter, tol, x_dtype, prod, flags)."""
 
     def __init__(self, X, r, **params):
         self._ctx = C.c_void_p()
