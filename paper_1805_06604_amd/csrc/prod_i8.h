@@ -21,8 +21,9 @@
 // [lane][16]. One wave load of an MFMA operand is then 1 KB of contiguous
 // memory, and a 16-row block streams its K-chunk front to back.
 //
-// Tiling. A workgroup is 4 waves over 128 rows x RP columns and one K-chunk;
-// each wave owns 32 rows (two 16-row MFMA blocks) and all RP/16 column blocks.
+// Tiling. A workgroup is 8 waves (two per SIMD) over 128 rows x RP columns
+// and one K-chunk; each wave owns 16 rows (one 16-row MFMA block) and all
+// RP/16 column blocks, so that one wave's multiplies overlap the other's waits.
 // K advances in tiles of 64 (one MFMA k-step). The slices of Z go straight
 // through a 3-stage LDS ring filled by direct global-to-LDS loads, two tiles
 // ahead of the multiply, one barrier per tile; the factor is sliced once per
@@ -37,8 +38,9 @@ namespace i8 {
 
 typedef int int32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kWaves = 4;
-constexpr int kWM = 32;                 // rows per wave
+constexpr int kWaves = 8;
+constexpr int kBPW = 1;                 // 16-row MFMA blocks per wave
+constexpr int kWM = 16 * kBPW;          // rows per wave
 constexpr int kBM = kWaves * kWM;       // rows per workgroup
 constexpr int kKT = 64;                 // K per tile (one MFMA k-step)
 constexpr int kSl = 4;                  // slices per value
@@ -134,10 +136,16 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
 {
     constexpr int NCB = RP / 16;
     constexpr int FT = kSl * RP * kKT;                // factor tile bytes
-    constexpr int ZW = 2 * kSl * 1024;                // Z bytes of one wave per tile
-    constexpr int STAGE = kWaves * ZW + FT;           // [Z of waves 0..3][factor tile]
-    constexpr int FW = FT / kWaves;                   // factor bytes moved per wave
-    constexpr int OPS = (ZW + FW) / 1024;             // direct loads per wave per tile
+    constexpr int ZW = kBPW * kSl * 1024;             // Z bytes of one wave per tile
+    constexpr int STAGE = kWaves * ZW + FT;           // [Z of the waves][factor tile]
+    // The factor tile (RP KB) is moved by the first NFW waves, NFW the largest
+    // of 8, 6, 4 that divides it into whole KB.
+    constexpr int FTK = FT / 1024;
+    constexpr int NFW = (FTK % 8 == 0) ? 8 : (FTK % 6 == 0) ? 6 : (FTK % 4 == 0) ? 4 : 1;
+    constexpr int FW = FT / NFW;                      // factor bytes moved per issuing wave
+    constexpr int OPS = (ZW + FW) / 1024;             // direct loads per issuing wave per tile
+    constexpr int OPS0 = ZW / 1024;                   // the other waves
+    static_assert(NFW <= kWaves, "enough waves to move the factor");
     static_assert(FW % 1024 == 0 && OPS <= 15, "tile splits evenly; vmcnt fits");
     __shared__ __attribute__((aligned(1024))) signed char ring[kStages][STAGE];
 
@@ -153,18 +161,17 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
     if (kend > a.ld) kend = a.ld;
     const int64_t row0 = rb * kBM + wave * kWM;
     const int64_t ntile = a.ld / kKT;
-    // The wave's two 16-row blocks are adjacent in the fragment layout only
-    // tile by tile: block b of tile t starts at ((row0/16 + b) ntile + t) 4 KB.
+    // The wave's 16-row block of tile t starts at ((row0/16) ntile + t) 4 KB in
+    // the fragment layout.
     const signed char *Z = static_cast<const signed char *>(a.Z);
     const signed char *zsrc0 = Z + (row0 / 16) * ntile * (kSl * 1024);
-    const signed char *zsrc1 = zsrc0 + ntile * (kSl * 1024);
     // This lane's byte offset of part g of column 16 c + lr, slice j, within
     // the factor tile: ((j RP + 16 c + lr) 4 + fpart) 16.
     const int boff = (lr * 4 + fpart(lr, g)) * 16;
 
-    int32x4 acc[2][NCB][kMaxW + 1];
+    int32x4 acc[kBPW][NCB][kMaxW + 1];
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < kBPW; ++b)
 #pragma unroll
         for (int c = 0; c < NCB; ++c)
 #pragma unroll
@@ -175,8 +182,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
     auto issue = [&](int64_t tile, int sg) {
         signed char *base = ring[sg];
         dma_wave<kSl * 1024>(base + wave * ZW, zsrc0 + tile * (kSl * 1024), lane);
-        dma_wave<kSl * 1024>(base + wave * ZW + kSl * 1024, zsrc1 + tile * (kSl * 1024), lane);
-        dma_wave<FW>(base + kWaves * ZW + wave * FW, a.Fsl + tile * FT + wave * FW, lane);
+        if (wave < NFW) dma_wave<FW>(base + kWaves * ZW + wave * FW, a.Fsl + tile * FT + wave * FW, lane);
     };
     if (t0 < t1) {
         issue(t0, 0);
@@ -187,7 +193,10 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
         // Tile t's loads (issued before the OPS loads of tile t + 1) have
         // landed; after the barrier every wave's share is visible and every
         // wave is done with the stage read in the previous iteration.
-        __builtin_amdgcn_s_waitcnt(0x0070 | OPS);     // vmcnt(OPS) lgkmcnt(0)
+        // (vmcnt(OPS or OPS0) lgkmcnt(0): the loads of one tile issue may
+        // remain in flight; the immediate encodes vmcnt below 16 in bits 3:0.)
+        if (wave < NFW) __builtin_amdgcn_s_waitcnt(0x0070 | OPS);
+        else __builtin_amdgcn_s_waitcnt(0x0070 | OPS0);
         __builtin_amdgcn_s_barrier();
         // Tile t + 2 (or a harmless reload of the last tile) into the stage
         // freed by tile t - 1.
@@ -195,9 +204,9 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
         issue(t + 2 < t1 ? t + 2 : t1 - 1, sn);
         const signed char *zt = ring[sg] + wave * ZW + 16 * lane;
         const signed char *ft = ring[sg] + kWaves * ZW;
-        int32x4 z[2][kSl];
+        int32x4 z[kBPW][kSl];
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < kBPW; ++b)
 #pragma unroll
             for (int p = 0; p < kSl; ++p)
                 z[b][p] = *reinterpret_cast<const int32x4 *>(zt + (b * kSl + p) * 1024);
@@ -212,7 +221,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
 #pragma unroll
             for (int i = 0; i + j <= kMaxW; ++i)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < kBPW; ++b)
 #pragma unroll
                     for (int c = 0; c < NCB; ++c)
                         acc[b][c][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
@@ -228,7 +237,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
 #pragma unroll
     for (int c = 0; c < NCB; ++c) te[c] = a.texp[c * 16 + lr];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < kBPW; ++b) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t row = row0 + 16 * b + 4 * g + i;
