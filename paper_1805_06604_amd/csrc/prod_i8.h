@@ -24,11 +24,17 @@
 // Tiling. A workgroup is 8 waves (two per SIMD) over 128 rows x RP columns
 // and one K-chunk; each wave owns 16 rows (one 16-row MFMA block) and all
 // RP/16 column blocks, so that one wave's multiplies overlap the other's waits.
-// K advances in tiles of 64 (one MFMA k-step). The slices of Z go straight
-// through a 3-stage LDS ring filled by direct global-to-LDS loads, two tiles
-// ahead of the multiply, one barrier per tile; the factor is sliced once per
-// product by its own kernel (in MFMA operand order) and each tile of it rides
-// in the same ring stage as the Z tile.
+// K advances in tiles of 64 (one MFMA k-step). Each wave streams the slices of
+// its own rows straight into registers, three tiles ahead of the multiply
+// (four register buffers), with non-temporal loads: Z is read once per product.
+// The factor is sliced once per product by its own kernel (in MFMA operand
+// order); its tiles, which all 8 waves read, go through a 4-stage LDS ring
+// filled by direct global-to-LDS loads in the same issue group as the Z tile,
+// one barrier per tile. The K loop is unrolled by the four buffers, so every
+// buffer and stage index is static, and every load is issued unconditionally
+// (the tile index clamped to the K-chunk: the loop starts one round early and
+// ends past the last tile with harmless reloads), so the wait counts are
+// static and no load precedes the loop.
 #pragma once
 
 #include "nmf_internal.h"
@@ -39,8 +45,7 @@ namespace i8 {
 typedef int int32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 8;
-constexpr int kBPW = 1;                 // 16-row MFMA blocks per wave
-constexpr int kWM = 16 * kBPW;          // rows per wave
+constexpr int kWM = 16;                 // rows per wave (one 16-row MFMA block)
 constexpr int kBM = kWaves * kWM;       // rows per workgroup
 constexpr int kKT = 64;                 // K per tile (one MFMA k-step)
 constexpr int kSl = 4;                  // slices per value
@@ -115,39 +120,29 @@ __device__ __forceinline__ void slice_body(const ProdArgs &a, int bid)
     }
 }
 
-// Direct global-to-LDS copy of `bytes` contiguous bytes (a multiple of 4 KB)
-// by one wave: 1 KB per instruction, lane l moving bytes 16 l .. 16 l + 15.
-template <int BYTES>
-__device__ __forceinline__ void dma_wave(signed char *lds, const signed char *src, int lane)
-{
-#pragma unroll
-    for (int q = 0; q < BYTES / 1024; ++q)
-        __builtin_amdgcn_global_load_lds(
-            (const __attribute__((address_space(1))) void *)(src + q * 1024 + 16 * lane),
-            (__attribute__((address_space(3))) void *)(lds + q * 1024), 16, 0, 0);
-}
+// s_waitcnt immediate: vmcnt(n) (bits 3:0 and 15:14), lgkmcnt(0), no expcnt wait.
+__host__ __device__ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0070; }
 
-// Stages of the LDS ring: tile t lives in stage t mod kStages; two tiles are
-// in flight while one is multiplied.
-constexpr int kStages = 3;
+constexpr int kDepth = 3;               // tiles in flight ahead of the multiply
+constexpr int kBufs = kDepth + 1;       // register buffers = LDS stages = K-loop unroll
 
 template <int RP>
-__device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
+__device__ __forceinline__ void prod_body(const ProdArgs &args, int bid)
 {
+    // A private copy: the grouped kernels read the arguments from global
+    // memory, which the compiler would otherwise reload (and wait for) after
+    // every direct-to-LDS load.
+    const ProdArgs a = args;
     constexpr int NCB = RP / 16;
-    constexpr int FT = kSl * RP * kKT;                // factor tile bytes
-    constexpr int ZW = kBPW * kSl * 1024;             // Z bytes of one wave per tile
-    constexpr int STAGE = kWaves * ZW + FT;           // [Z of the waves][factor tile]
-    // The factor tile (RP KB) is moved by the first NFW waves, NFW the largest
-    // of 8, 6, 4 that divides it into whole KB.
+    constexpr int FT = kSl * RP * kKT;                // factor tile bytes (RP KB)
     constexpr int FTK = FT / 1024;
-    constexpr int NFW = (FTK % 8 == 0) ? 8 : (FTK % 6 == 0) ? 6 : (FTK % 4 == 0) ? 4 : 1;
-    constexpr int FW = FT / NFW;                      // factor bytes moved per issuing wave
-    constexpr int OPS = (ZW + FW) / 1024;             // direct loads per issuing wave per tile
-    constexpr int OPS0 = ZW / 1024;                   // the other waves
-    static_assert(NFW <= kWaves, "enough waves to move the factor");
-    static_assert(FW % 1024 == 0 && OPS <= 15, "tile splits evenly; vmcnt fits");
-    __shared__ __attribute__((aligned(1024))) signed char ring[kStages][STAGE];
+    // Every wave moves FOPS KB of each factor tile (the last KB again where the
+    // tile does not split evenly: identical bytes to the same place), so all
+    // waves issue the same number of loads per tile.
+    constexpr int FOPS = (FTK + kWaves - 1) / kWaves;
+    constexpr int GOPS = kSl + FOPS;                  // loads per wave per tile
+    static_assert((kDepth - 1) * GOPS <= 63, "vmcnt range");
+    __shared__ __attribute__((aligned(1024))) signed char ring[kBufs][FT];
 
     const DevState *st = a.st;
     if (a.sel != SEL_SLOT0 && st->done) return;
@@ -162,74 +157,81 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
     const int64_t row0 = rb * kBM + wave * kWM;
     const int64_t ntile = a.ld / kKT;
     // The wave's 16-row block of tile t starts at ((row0/16) ntile + t) 4 KB in
-    // the fragment layout.
-    const signed char *Z = static_cast<const signed char *>(a.Z);
-    const signed char *zsrc0 = Z + (row0 / 16) * ntile * (kSl * 1024);
+    // the fragment layout; this lane's 16 bytes of slice p at p KB + 16 lane.
+    const signed char *zsrc = static_cast<const signed char *>(a.Z) +
+                              (row0 / 16) * ntile * (kSl * 1024) + 16 * lane;
     // This lane's byte offset of part g of column 16 c + lr, slice j, within
     // the factor tile: ((j RP + 16 c + lr) 4 + fpart) 16.
     const int boff = (lr * 4 + fpart(lr, g)) * 16;
 
-    int32x4 acc[kBPW][NCB][kMaxW + 1];
+    int32x4 acc[NCB][kMaxW + 1];
 #pragma unroll
-    for (int b = 0; b < kBPW; ++b)
+    for (int c = 0; c < NCB; ++c)
 #pragma unroll
-        for (int c = 0; c < NCB; ++c)
-#pragma unroll
-            for (int w = 0; w <= kMaxW; ++w) acc[b][c][w] = int32x4{0, 0, 0, 0};
+        for (int w = 0; w <= kMaxW; ++w) acc[c][w] = int32x4{0, 0, 0, 0};
 
     const int64_t t0 = kbeg / kKT, t1 = (kend + kKT - 1) / kKT;   // tiles [t0, t1)
-    // Issues the direct loads of tile `tile` into stage `sg` (OPS per wave).
-    auto issue = [&](int64_t tile, int sg) {
-        signed char *base = ring[sg];
-        dma_wave<kSl * 1024>(base + wave * ZW, zsrc0 + tile * (kSl * 1024), lane);
-        if (wave < NFW) dma_wave<FW>(base + kWaves * ZW + wave * FW, a.Fsl + tile * FT + wave * FW, lane);
-    };
     if (t0 < t1) {
-        issue(t0, 0);
-        issue(t0 + 1 < t1 ? t0 + 1 : t0, 1);
-    }
-    int sg = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-        // Tile t's loads (issued before the OPS loads of tile t + 1) have
-        // landed; after the barrier every wave's share is visible and every
-        // wave is done with the stage read in the previous iteration.
-        // (vmcnt(OPS or OPS0) lgkmcnt(0): the loads of one tile issue may
-        // remain in flight; the immediate encodes vmcnt below 16 in bits 3:0.)
-        if (wave < NFW) __builtin_amdgcn_s_waitcnt(0x0070 | OPS);
-        else __builtin_amdgcn_s_waitcnt(0x0070 | OPS0);
-        __builtin_amdgcn_s_barrier();
-        // Tile t + 2 (or a harmless reload of the last tile) into the stage
-        // freed by tile t - 1.
-        const int sn = (sg + 2 >= kStages) ? sg + 2 - kStages : sg + 2;
-        issue(t + 2 < t1 ? t + 2 : t1 - 1, sn);
-        const signed char *zt = ring[sg] + wave * ZW + 16 * lane;
-        const signed char *ft = ring[sg] + kWaves * ZW;
-        int32x4 z[kBPW][kSl];
+        int32x4 z[kBufs][kSl];
+        // Issue group of tile `tile` (clamped to [t0, t1)): this wave's
+        // share of the factor tile into stage `sg`, then its Z slices into zb.
+        auto issue = [&](int64_t tile, int sg, int32x4 (&zb)[kSl]) {
+            if (tile < t0) tile = t0;
+            if (tile > t1 - 1) tile = t1 - 1;
+            const signed char *fs = a.Fsl + tile * FT + 16 * lane;
 #pragma unroll
-        for (int b = 0; b < kBPW; ++b)
+            for (int q = 0; q < FOPS; ++q) {
+                const int kb = (wave * FOPS + q < FTK) ? wave * FOPS + q : FTK - 1;
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(fs + kb * 1024),
+                    (__attribute__((address_space(3))) void *)(ring[sg] + kb * 1024), 16, 0, 0);
+            }
+            const signed char *zp = zsrc + tile * (kSl * 1024);
 #pragma unroll
             for (int p = 0; p < kSl; ++p)
-                z[b][p] = *reinterpret_cast<const int32x4 *>(zt + (b * kSl + p) * 1024);
-        // Factor slice j against Z slices i <= kMaxW - j; consecutive MFMAs
-        // cycle through the 2 x NCB output blocks.
+                zb[p] = __builtin_nontemporal_load(reinterpret_cast<const int32x4 *>(zp + p * 1024));
+        };
+        // The loop starts kBufs tiles early: its first round only issues the
+        // groups of tiles t0 .. t0 + kDepth - 1 (and a harmless load of tile
+        // t0 into the buffer of t0 - 1), so that no load precedes the loop and
+        // the register buffers need no copies at its head.
+        for (int64_t tb = t0 - kBufs; tb < t1; tb += kBufs) {
+            static_for<kBufs>([&](auto UU) {
+                constexpr int u = decltype(UU)::value;          // tile tb + u: buffer and stage u
+                constexpr int un = (u + kDepth) % kBufs;        // freed by tile tb + u - 1
+                const int64_t t = tb + u;
+                // Tile t's group has landed once at most the kDepth - 1 later
+                // groups are in flight; after the barrier every wave's share of
+                // the factor tile is visible, and every wave is done with the
+                // stage read for tile t - 1. (The scheduling barriers keep the
+                // wait, the barrier and the issue group in this order.)
+                __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm((kDepth - 1) * GOPS));
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_sched_barrier(0);
+                issue(t + kDepth, un, z[un]);
+                __builtin_amdgcn_sched_barrier(0);
+                if (t >= t0 && t < t1) {                        // (uniform)
+                    const signed char *ft = ring[u];
+                    // Factor slice j against Z slices i <= kMaxW - j.
 #pragma unroll
-        for (int j = 0; j < kSl; ++j) {
-            int32x4 bp[NCB];
+                    for (int j = 0; j < kSl; ++j) {
+                        int32x4 bp[NCB];
 #pragma unroll
-            for (int c = 0; c < NCB; ++c)
-                bp[c] = *reinterpret_cast<const int32x4 *>(ft + (j * RP + 16 * c) * 64 + boff);
+                        for (int c = 0; c < NCB; ++c)
+                            bp[c] = *reinterpret_cast<const int32x4 *>(ft + (j * RP + 16 * c) * 64 + boff);
 #pragma unroll
-            for (int i = 0; i + j <= kMaxW; ++i)
+                        for (int i = 0; i + j <= kMaxW; ++i)
 #pragma unroll
-                for (int b = 0; b < kBPW; ++b)
-#pragma unroll
-                    for (int c = 0; c < NCB; ++c)
-                        acc[b][c][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                            z[b][i], bp[c], acc[b][c][i + j], 0, 0, 0);
+                            for (int c = 0; c < NCB; ++c)
+                                acc[c][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                    z[u][i], bp[c], acc[c][i + j], 0, 0, 0);
+                    }
+                }
+            });
         }
-        sg = (sg + 1 == kStages) ? 0 : sg + 1;
+        __builtin_amdgcn_s_waitcnt(0x0070);            // vmcnt(0): no load outlives the loop
     }
-    __builtin_amdgcn_s_waitcnt(0x0070);                // vmcnt(0): no load outlives the loop
 
     // D layout: lane holds column lr of each block, rows 4g..4g+3.
     double *Y = a.Y + (size_t)kc * a.rows_pad * RP;
@@ -237,18 +239,15 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, int bid)
 #pragma unroll
     for (int c = 0; c < NCB; ++c) te[c] = a.texp[c * 16 + lr];
 #pragma unroll
-    for (int b = 0; b < kBPW; ++b) {
+    for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + 4 * g + i;
+        const int se = a.zexp[row];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t row = row0 + 16 * b + 4 * g + i;
-            const int se = a.zexp[row];
+        for (int c = 0; c < NCB; ++c) {
+            double v = 0.0;
 #pragma unroll
-            for (int c = 0; c < NCB; ++c) {
-                double v = 0.0;
-#pragma unroll
-                for (int w = kMaxW; w >= 0; --w) v = v * (1.0 / 128.0) + (double)acc[b][c][w][i];
-                Y[row * RP + c * 16 + lr] = ldexp(v, -se - te[c]);
-            }
+            for (int w = kMaxW; w >= 0; --w) v = v * (1.0 / 128.0) + (double)acc[c][w][i];
+            Y[row * RP + c * 16 + lr] = ldexp(v, -se - te[c]);
         }
     }
 }
