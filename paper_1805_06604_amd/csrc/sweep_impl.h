@@ -317,11 +317,14 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                         const double gq = s_tri[b][q][lr];
                         // Stage by stage over the four independent rows of
                         // the lane, so that their latencies overlap.
+                        // The change max(x + t/G_kk, 0) - x, formed as
+                        // max(t/G_kk, -x): equal up to rounding, one step
+                        // shorter.
                         double d[4];
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) d[v] = fma(t[v], inv[b], xd[b][v]);
+                        for (int v = 0; v < 4; ++v) d[v] = t[v] * inv[b];
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) d[v] = fmax(d[v], 0.0) - xd[b][v];
+                        for (int v = 0; v < 4; ++v) d[v] = fmax(d[v], -xd[b][v]);
 #pragma unroll
                         for (int v = 0; v < 4; ++v) d[v] = row_bcast<q>(d[v]);
 #pragma unroll
