@@ -102,21 +102,28 @@ __device__ __forceinline__ void slice_body(const ProdArgs &a, int bid)
     __syncthreads();
     const int64_t tile = bid;
     uint32_t *out = reinterpret_cast<uint32_t *>(a.Fsl + tile * (kSl * RP * kKT));
-    for (int item = tid; item < RP * (kKT / 4); item += 256) {
-        const int c = item % RP, kq = item / RP;
-        uint32_t w[kSl] = {0u, 0u, 0u, 0u};
+    // One item per thread (RP x 4 <= 256): column c, the 16 rows of part
+    // `part`; all 16 loads are issued before any store.
+    for (int item = tid; item < RP * 4; item += 256) {
+        const int c = item % RP, part = item / RP;
+        float f[16];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t k = tile * kKT + 4 * kq + e;
-            const float f = (k < a.K) ? F[k * RP + c] : 0.0f;
+        for (int e = 0; e < 16; ++e) {
+            const int64_t k = tile * kKT + 16 * part + e;
+            f[e] = (k < a.K) ? F[k * RP + c] : 0.0f;
+        }
+        uint32_t w[kSl][4] = {};
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
             int d[kSl];
-            slice4(ldexpf(f, s_texp[c]), d);
+            slice4(ldexpf(f[e], s_texp[c]), d);
 #pragma unroll
-            for (int p = 0; p < kSl; ++p) w[p] |= ((uint32_t)(d[p] & 0xff)) << (8 * e);
+            for (int p = 0; p < kSl; ++p) w[p][e / 4] |= ((uint32_t)(d[p] & 0xff)) << (8 * (e % 4));
         }
 #pragma unroll
         for (int p = 0; p < kSl; ++p)
-            out[(p * RP + c) * (kKT / 4) + fpart(c, kq / 4) * 4 + kq % 4] = w[p];
+            *reinterpret_cast<uint4 *>(out + (p * RP + c) * (kKT / 4) + fpart(c, part) * 4) =
+                make_uint4(w[p][0], w[p][1], w[p][2], w[p][3]);
     }
 }
 
