@@ -66,6 +66,12 @@ def parse():
     ap.add_argument("--serve-seq", type=int, default=16,
                     help="requests of the same stream solved one at a time (baseline)")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-qps-low", type=float, default=100.0,
+                    help="second arrival rate, below saturation (0: skip)")
+    ap.add_argument("--x16-steps", type=int, default=50,
+                    help="timed steps of the 16-bit X runs (BF16, FP16; 0: skip)")
+    ap.add_argument("--k1-steps", type=int, default=50,
+                    help="timed steps of the run with one inner sweep (0: skip)")
     ap.add_argument("--eanls-steps", type=int, default=20,
                     help="timed E-ANLS iterations on the same workload (0 disables)")
     ap.add_argument("--adaptive-steps", type=int, default=20,
@@ -203,14 +209,50 @@ def adaptive(args, P, p, stream, torch):
             "rho_final": float(res.trace[-1])}
 
 
-def serving(args, P, S):
+def variant(args, P, S, p, stream, torch, x_dtype, prod, K, steps, label):
+    """The headline run (same workload, parameters, warm-up and timing) with
+    another X storage, product kernel or inner sweep count."""
+    m, n, r = args.m, args.n, args.r
+    total = args.warmup + steps + args.profile_iters
+    xd = {"f32": P.XDtype.F32, "bf16": P.XDtype.BF16, "f16": P.XDtype.F16}[x_dtype]
+    pm = {"auto": P.Prod.AUTO, "exact": P.Prod.MFMA_EXACT, "fast": P.Prod.MFMA_FAST}[prod]
+    solver = P.Solver(p.X, r, hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
+                      inner_k=K, max_iter=total, x_dtype=xd, prod=pm)
+    W0, H0 = S.init_factors(m, n, r, 0)
+    solver.start(W0, H0, stream=stream)
+    solver.iterate(args.warmup, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    solver.iterate(steps, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    ph = solver.profile(args.profile_iters, stream=stream)
+    res = solver.read(stream=stream)
+    solver.close()
+    sx = XBYTES[x_dtype]
+    nbytes = (m * n * sx + m * r * 4 + n * r * 8) + (m * n * sx + n * r * 4 + m * r * 8)
+    achieved = nbytes / ((ph["prod_ct"] + ph["prod_a"]) * 1e-3) / 1e9
+    return res.trace, {
+        "workload": label, "x_dtype": x_dtype, "prod": prod, "inner_k": K,
+        "value": 1e3 / ms, "unit": "iters/s", "ms_per_step": ms, "steps": steps, "phase_ms": ph,
+        "rho_final": float(res.trace[-1]),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "X-streaming product", "bytes_per_launch": 0.5 * nbytes,
+                     "ms_per_launch": 0.5 * (ph["prod_ct"] + ph["prod_a"])}}
+
+
+def serving(args, P, S, qps, n_seq):
     """Batched solves of a Poisson stream of small problems (m, n ~
     U{64..2048}, r in {5, 10, 20, 40}, X = max(0, W H + 1% noise)), each run
     to 200 iterations or |rho(k) - rho(k-1)| < 1e-6, replayed in real time:
     a request is submitted once its arrival time has passed, its latency runs
     from arrival to its result on the host. The baseline solves the first
     requests of the same stream one at a time (one context each)."""
-    reqs = S.requests(count=args.serve_requests, qps=args.serve_qps, seed=0)
+    reqs = S.requests(count=args.serve_requests, qps=qps, seed=0)
     t_gen = time.perf_counter()
     probs = [S.request_problem(q) for q in reqs]
     t_gen = time.perf_counter() - t_gen
@@ -241,29 +283,30 @@ def serving(args, P, S):
                 time.sleep(max(0.0, reqs[nxt].t_arrive - (time.perf_counter() - t0)))
         wall = time.perf_counter() - t0
     lat_ms = np.sort(np.asarray(lat) * 1e3)
-    n_seq = min(args.serve_seq, len(reqs))
-    t1 = time.perf_counter()
-    for p in probs[:n_seq]:
-        with P.Solver(p.X, p.r, prod=P.Prod.MFMA_EXACT, **kw) as sv:
-            sv.solve(p.W0, p.H0)
-    seq = n_seq / (time.perf_counter() - t1)
     span = wall - reqs[0].t_arrive
-    return {
-        "workload": (f"{len(reqs)} Poisson requests at {args.serve_qps:g} QPS, m, n ~ U{{64..2048}}, "
+    out = {
+        "workload": (f"{len(reqs)} Poisson requests at {qps:g} QPS, m, n ~ U{{64..2048}}, "
                      f"r in {{5,10,20,40}}, <= 200 iterations or tol 1e-6"),
         "solves_per_s": len(reqs) / span, "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)), "max_ms": float(lat_ms[-1]),
-        "mean_iters": float(np.mean(iters)),
-        "sequential_solves_per_s": seq, "sequential_requests": n_seq,
-        "speedup_vs_sequential": len(reqs) / span / seq,
-        "generation_s": t_gen,
+        "mean_iters": float(np.mean(iters)), "generation_s": t_gen,
     }
+    n_seq = min(n_seq, len(reqs))
+    if n_seq > 0:
+        t1 = time.perf_counter()
+        for p in probs[:n_seq]:
+            with P.Solver(p.X, p.r, prod=P.Prod.MFMA_EXACT, **kw) as sv:
+                sv.solve(p.W0, p.H0)
+        seq = n_seq / (time.perf_counter() - t1)
+        out.update({"sequential_solves_per_s": seq, "sequential_requests": n_seq,
+                    "speedup_vs_sequential": len(reqs) / span / seq})
+    return out
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
 
@@ -289,7 +332,6 @@ def main():
     ad = adaptive(args, P, p, stream, torch) if args.adaptive_steps > 0 else None
     solver = P.Solver(p.X, r, hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
                       inner_k=K, max_iter=total, x_dtype=xd, prod=pm)
-    del p
     W0, H0 = S.init_factors(m, n, r, 0)
     solver.start(W0, H0, stream=stream)
     solver.iterate(args.warmup, stream=stream)
@@ -345,12 +387,30 @@ def main():
                      "traffic": traffic, "kernel": "X-streaming product",
                      "bytes_per_launch": 0.5 * (bytes_ct + bytes_a), "ms_per_launch": prod_ms},
     }
+    # The same run with X stored in 16 bits (matrix-core products on BF16
+    # parts), its final error set against the FP32 run's at the same
+    # iteration; and with one inner sweep per block.
+    if args.x16_steps > 0 and args.x_dtype == "f32":
+        for xd16 in ("bf16", "f16"):
+            tr, v = variant(args, P, S, p, stream, torch, xd16, "fast", K, args.x16_steps,
+                            f"planted dense {m}x{n} r={r}, X stored as {xd16}, K={K}")
+            k = min(len(tr), len(res.trace)) - 1
+            v["rho_f32_same_iter"] = float(res.trace[k])
+            v["abs_rho_gap_vs_f32"] = float(abs(tr[k] - res.trace[k]))
+            out[f"x_{xd16}"] = v
+    if args.k1_steps > 0:
+        _, v = variant(args, P, S, p, stream, torch, args.x_dtype, args.prod, 1, args.k1_steps,
+                       f"planted dense {m}x{n} r={r}, one inner sweep per block (K=1)")
+        out["inner_k1"] = v
+    del p
     if ea is not None:
         out["eanls"] = ea
     if ad is not None:
         out["adaptive_inner"] = ad
     if args.serve_requests > 0:
-        out["serving"] = serving(args, P, S)
+        out["serving"] = serving(args, P, S, args.serve_qps, args.serve_seq)
+        if args.serve_qps_low > 0:
+            out["serving_below_saturation"] = serving(args, P, S, args.serve_qps_low, 0)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)

@@ -33,7 +33,7 @@ typedef struct nmf_ctx nmf_ctx;
 typedef enum {
     NMF_OK = 0,
     NMF_E_INVAL = 1,        /* an argument is out of its documented domain   */
-    NMF_E_UNSUPPORTED = 2,  /* valid, but not provided by this build         */
+    NMF_E_UNSUPPORTED = 2,  /* valid, but not supported by the library       */
     NMF_E_NOMEM = 3,        /* host or device allocation failed              */
     NMF_E_DEVICE = 4,       /* a HIP call failed                             */
     NMF_E_NUMERIC = 5,      /* the initial error e(0) is not finite          */

@@ -79,14 +79,15 @@ int choose_kernel(const nmf_params *p, int fmt)
     switch (p->prod) {
     case NMF_PROD_VALU: return nmf::PK_VALU;
     case NMF_PROD_MFMA_EXACT: return nmf::PK_MFMA_I8;
-    case NMF_PROD_MFMA_FAST: return nmf::PK_MFMA_L1;
-    default: return p->x_dtype == NMF_X_F32 ? nmf::PK_MFMA_I8 : nmf::PK_MFMA_L1;
+    case NMF_PROD_MFMA_FAST: return p->x_dtype == NMF_X_F32 ? nmf::PK_MFMA_L1 : nmf::PK_MFMA_X16;
+    default: return p->x_dtype == NMF_X_F32 ? nmf::PK_MFMA_I8 : nmf::PK_MFMA_X16;
     }
 }
 
-// Split-K plan of one product: enough workgroups of 128 rows to fill the chip
-// (about 512 for the kernels that run two per CU, 256 for the exact-integer
-// kernel, whose LDS ring takes a whole CU), K-chunks of whole 64-column tiles.
+// Split-K plan of one product: enough workgroups of 128 rows (256 for the
+// 16-bit kernel) to fill the chip (about 512 for the kernels that run two per
+// CU, 256 for the exact-integer and 16-bit kernels, whose 8-wave workgroups
+// take a whole CU), K-chunks of whole 64-column tiles.
 void plan_product(nmf::ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, int64_t K,
                   int64_t ld, int64_t target_wg = 0)
 {
@@ -99,8 +100,9 @@ void plan_product(nmf::ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, 
         a.kchunk = ld;
         return;
     }
-    const int64_t rb = rows_pad / 128, tiles = ld / 64;
-    const int64_t target = target_wg > 0 ? target_wg : (kernel == nmf::PK_MFMA_I8) ? 256 : 512;
+    const int64_t rb = rows_pad / (kernel == nmf::PK_MFMA_X16 ? nmf::kX16Rows : 128), tiles = ld / 64;
+    const bool whole_cu = kernel == nmf::PK_MFMA_I8 || kernel == nmf::PK_MFMA_X16;
+    const int64_t target = target_wg > 0 ? target_wg : whole_cu ? 256 : 512;
     int64_t want = (target + rb - 1) / rb;
     // The exact-integer sums stay below 2^31 for chunks of at most 65536.
     if (kernel == nmf::PK_MFMA_I8) want = std::max<int64_t>(want, (tiles + 1023) / 1024);
@@ -245,9 +247,10 @@ nmf_status alloc_buffers(nmf_ctx *c)
         HIP_TRY(c, dalloc(&b.sweeps, (size_t)2 * std::max(c->p.max_iter, 1)));
         HIP_TRY(c, hipMemsetAsync(b.sweeps, 0, sizeof(int32_t) * 2 * std::max(c->p.max_iter, 1), c->own));
     }
-    if (c->prod_kernel == nmf::PK_MFMA_I8) {
+    if (c->prod_kernel == nmf::PK_MFMA_I8 || c->prod_kernel == nmf::PK_MFMA_X16) {
         // Both products slice their factor into one shared buffer (they run in
-        // stream order): (ld / 64) tiles of 4 slices x RP columns x 64 rows.
+        // stream order): (ld / 64) tiles of 4 slices x RP columns x 64 rows
+        // (int8), or of 2 k-steps x 2 BF16 parts x RP columns x 32 rows.
         HIP_TRY(c, dalloc(&b.fsl, (size_t)std::max(c->ldx, c->ldxt) * 4 * rp));
         HIP_TRY(c, dalloc(&b.texp, (size_t)rp));
     }
@@ -302,6 +305,19 @@ nmf_status upload_dense(nmf_ctx *c, const nmf_matrix *X)
         (void)hipFree(c->Xt);
         c->X = xs;
         c->Xt = xts;
+    }
+    if (c->prod_kernel == nmf::PK_MFMA_X16) {
+        // Keep X and X^T in 16 bits, in the fragment order the product streams.
+        void *xf = nullptr, *xtf = nullptr;
+        HIP_TRY(c, hipMalloc(&xf, xsz));
+        HIP_TRY(c, hipMalloc(&xtf, xtsz));
+        HIP_TRY(c, nmf::x16::to_fragments(c->X, c->b.m_pad, c->ldx, xf, c->own));
+        HIP_TRY(c, nmf::x16::to_fragments(c->Xt, c->b.n_pad, c->ldxt, xtf, c->own));
+        HIP_TRY(c, hipStreamSynchronize(c->own));
+        (void)hipFree(c->X);
+        (void)hipFree(c->Xt);
+        c->X = xf;
+        c->Xt = xtf;
     }
     return NMF_OK;
 }
@@ -503,8 +519,9 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
     c->rp = round_rank(p->r);
     c->fmt = X->fmt;
     c->prod_kernel = choose_kernel(p, X->fmt);
-    c->b.m_pad = round_up(c->m, 128);
-    c->b.n_pad = round_up(c->n, 128);
+    const int64_t row_q = (c->prod_kernel == nmf::PK_MFMA_X16) ? nmf::kX16Rows : 128;
+    c->b.m_pad = round_up(c->m, row_q);
+    c->b.n_pad = round_up(c->n, row_q);
     c->ldx = round_up(c->n, 64);
     c->ldxt = round_up(c->m, 64);
     plan_product(c->pa, c->prod_kernel, c->m, c->b.m_pad, c->n, c->ldx);

@@ -182,6 +182,9 @@ __global__ void sum_parts_kernel(const double *__restrict__ part, int nblk, doub
 namespace i8 {
 void launch(int rp, const ProdArgs &a, hipStream_t s, hipEvent_t mid);
 }
+namespace x16 {
+hipError_t launch(int rp, int xdtype, const ProdArgs &a, hipStream_t s, hipEvent_t mid);
+}
 namespace csr {
 hipError_t launch(int rp, const ProdArgs &a, hipStream_t s);
 }
@@ -199,6 +202,7 @@ hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hip
         i8::launch(rp, a, s, mid);
         return hipGetLastError();
     }
+    if (kernel == PK_MFMA_X16) return x16::launch(rp, xdtype, a, s, mid);
     // No slicing step: the "between" mark goes before the product.
     if (mid) (void)hipEventRecord(mid, s);
     if (kernel == PK_CSR) return csr::launch(rp, a, s);

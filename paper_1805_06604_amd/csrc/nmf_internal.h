@@ -25,6 +25,9 @@ __device__ __forceinline__ void static_for(F &&f)
 // extrapolated point. Which buffer plays which role lives in DevState, so an
 // accept or a restart (Algorithm 2) is an index flip taken on the device.
 constexpr int kSlots = 3;
+// Rows of one workgroup of the 16-bit product: the row padding of X and X^T
+// (and of the factors) when that product is used; 128 otherwise.
+constexpr int kX16Rows = 256;
 
 // Factor rows handled by one workgroup of the sweep kernels (16 per wave).
 constexpr int kRowsPerBlock = 64;
@@ -127,7 +130,8 @@ struct ProdArgs {
     const int *zexp;
     const double *gram_base;
     int64_t gram_slot_stride;
-    signed char *Fsl;       // the factor in int8 slices: (ld / 64) x 4 x RP x 64
+    signed char *Fsl;       // the factor in int8 slices: (ld / 64) x 4 x RP x 64, or
+                            // (16-bit X) in two BF16 parts: (ld / 64) x 2 x 2 x RP x 64 B
     int *texp;              // its column scale exponents (RP)
     // Sparse kernel only: the CSR operand (host pointer to its plan).
     const CsrPlan *csr;
@@ -136,8 +140,10 @@ struct ProdArgs {
 // Product kernels: VALU FP64 FMA over FP32 operands (products exact, sums in
 // FP64), or matrix cores with operands split into BF16 parts keeping the part
 // pairs of relative weight >= 2^-8 (L = 1) or >= 2^-16 (L = 2), summed in
-// FP32 within a K-chunk.
-enum ProdKernel { PK_VALU = 0, PK_MFMA_L1 = 1, PK_MFMA_L2 = 2, PK_MFMA_I8 = 3, PK_CSR = 4 };
+// FP32 within a K-chunk (PK_MFMA_X16: the L = 1 product for 16-bit X stored
+// in fragment order, with the factor split once per product).
+enum ProdKernel { PK_VALU = 0, PK_MFMA_L1 = 1, PK_MFMA_L2 = 2, PK_MFMA_I8 = 3, PK_CSR = 4,
+                  PK_MFMA_X16 = 5 };
 
 // Device buffers of one context. Factors are FP32, row-major with RP columns
 // (r rounded up to a multiple of 16; the padding stays zero):
@@ -162,7 +168,7 @@ struct Buffers {
     double *beta_used = nullptr;
     double *beta_star = nullptr; // max_iter + 1: the beta* diagnostic (when enabled)
     float *stage = nullptr;  // staging of W0 / H0 / outputs: (m + n) * r
-    signed char *fsl = nullptr; // exact-integer products: the sliced factor (shared)
+    signed char *fsl = nullptr; // exact-integer / 16-bit products: the sliced or split factor (shared)
     int *texp = nullptr;     // and its column exponents
     // Adaptive inner loop: the factor being updated in FP64 between its
     // sweeps (max(m, n) x RP), the per-workgroup squared changes of a sweep,
@@ -237,6 +243,12 @@ hipError_t launch_unpack(int rp, int64_t m, int64_t n, int r, const Buffers &b,
 namespace i8 {
 hipError_t slice_rows(const void *src, int xdtype, int64_t rows, int64_t cols, int64_t ld_src,
                       int64_t ld_dst, void *dst, int *zexp, hipStream_t s);
+}
+
+// 16-bit path: copies a row-major 16-bit matrix (rows_pad x ld, ld a multiple
+// of 64) into the fragment order of the 16-bit product (same size).
+namespace x16 {
+hipError_t to_fragments(const void *src, int64_t rows_pad, int64_t ld, void *dst, hipStream_t s);
 }
 
 // X conversion at create: source FP32 (m x n) -> X (rows of length ldx) and

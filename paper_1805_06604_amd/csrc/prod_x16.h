@@ -1,0 +1,278 @@
+// X-streaming products for X stored in 16 bits (BF16 or FP16) on the BF16
+// matrix cores (arXiv 1805.06604: the W^T X and X H^T terms of the HALS
+// updates, section 1 and Remark 1).
+//
+// Precision. The factor is split once per product into two BF16 parts,
+// f = f0 + f1 + (at most 2^-16 |f|), round to nearest at each step. BF16 X is
+// one part; FP16 X is split on the fly into two (exact). The part pairs of
+// relative weight >= 2^-8 are kept (x0 f0, x0 f1, and x1 f0 for FP16) and
+// accumulated in FP32 on v_mfma_f32_16x16x32_bf16 within the K-chunk; the
+// K-chunk partials are written in FP64 and summed by the sweep kernels.
+//
+// Z layout (fragment order). The 16-bit copy of Z (X or the resident X^T) is
+// stored per 16-row block and 64-column tile as 2 k-steps x 64 lanes x 16
+// bytes, lane lr + 16 g holding row lr, columns 32 s + 8 g .. 32 s + 8 g + 7
+// of the tile: [row / 16][tile][k-step][lane][8]. One wave load of an MFMA
+// operand is then 1 KB of contiguous memory.
+//
+// Tiling (as in the exact-integer product, with two row blocks per wave so
+// that each factor operand read from LDS serves 32 rows). A workgroup is 8
+// waves (two per SIMD) over 256 rows x RP columns and one K-chunk; each wave
+// owns two 16-row blocks and all RP/16 column blocks, streams its Z fragments
+// straight into
+// registers three tiles ahead with non-temporal loads, and reads the split
+// factor tile from a 4-stage LDS ring filled by direct global-to-LDS loads in
+// the same issue group; one barrier per tile. The K loop is unrolled by the
+// four buffers and every load is issued unconditionally (tile index clamped
+// to the K-chunk), so the wait counts are static.
+#pragma once
+
+#include "nmf_internal.h"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+namespace nmf {
+namespace x16 {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef int int32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 8;
+constexpr int kBPW = 2;                 // 16-row MFMA blocks per wave
+constexpr int kWM = 16 * kBPW;          // rows per wave
+constexpr int kBM = kWaves * kWM;       // rows per workgroup
+static_assert(kBM == kX16Rows, "row padding of the 16-bit path");
+constexpr int kKT = 64;                 // K per tile (two MFMA k-steps)
+constexpr int kFP = 2;                  // BF16 parts of the factor
+constexpr int kTPS = 1;                 // tiles per step (one barrier per step)
+constexpr int kDepth = 3;               // steps in flight ahead of the multiply
+constexpr int kBufs = kDepth + 1;       // register buffers = LDS stages = K-loop unroll
+
+// Position of the 16-byte group g (k = 8 g .. 8 g + 7 of a k-step) of factor
+// column c in the split tile: XOR-swizzled by (c / 4) mod 4, so that the 16
+// lanes reading one group of 16 consecutive columns hit distinct LDS banks.
+__host__ __device__ constexpr int fgroup(int c, int g) { return g ^ ((c >> 2) & 3); }
+
+// s_waitcnt immediate: vmcnt(n) (bits 3:0 and 15:14), lgkmcnt(0), no expcnt wait.
+__host__ __device__ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0070; }
+
+// Splits one 64-row tile of the factor F (K x RP, FP32) per workgroup into
+// Fsp[tile][k-step][part][column][4 groups of 16 B] (BF16, B-operand order,
+// groups swizzled by fgroup, zero past K).
+template <int RP>
+__device__ __forceinline__ void split_body(const ProdArgs &a, int bid)
+{
+    const DevState *st = a.st;
+    int slot = 0;
+    if (a.sel != SEL_SLOT0) {
+        if (st->done) return;
+        slot = (a.sel == SEL_W_Y) ? st->w_y : (st->hp == 1 ? st->h_n : st->h_yn);
+    }
+    const float *__restrict__ F = a.F_base + slot * a.slot_stride;
+    const int64_t tile = bid;
+    signed char *out = a.Fsl + tile * (2 * kFP * RP * 64);
+    // One item per (k-step s, column c, group g): 8 rows, both parts.
+    for (int item = threadIdx.x; item < 2 * RP * 4; item += 256) {
+        const int c = item % RP, g = (item / RP) % 4, s = item / (4 * RP);
+        float f[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t k = tile * kKT + 32 * s + 8 * g + e;
+            f[e] = (k < a.K) ? F[k * RP + c] : 0.0f;
+        }
+        bf16x8 p0, p1;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const __bf16 h = (__bf16)f[e];
+            p0[e] = h;
+            p1[e] = (__bf16)(f[e] - (float)h);
+        }
+        *reinterpret_cast<bf16x8 *>(out + ((s * kFP + 0) * RP + c) * 64 + fgroup(c, g) * 16) = p0;
+        *reinterpret_cast<bf16x8 *>(out + ((s * kFP + 1) * RP + c) * 64 + fgroup(c, g) * 16) = p1;
+    }
+}
+
+// The MFMA A operand(s) of 8 X values held as 16 raw bytes.
+template <typename XT> struct XOps;
+template <> struct XOps<__hip_bfloat16> {
+    static constexpr int n = 1;
+    __device__ static void get(const int32x4 &raw, bf16x8 (&x)[1])
+    {
+        x[0] = __builtin_bit_cast(bf16x8, raw);
+    }
+};
+template <> struct XOps<__half> {
+    static constexpr int n = 2;
+    __device__ static void get(const int32x4 &raw, bf16x8 (&x)[2])
+    {
+        const half8 h = __builtin_bit_cast(half8, raw);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float f = (float)h[e];
+            const __bf16 a = (__bf16)f;
+            x[0][e] = a;
+            x[1][e] = (__bf16)(f - (float)a);   // exact: 11 significant bits in all
+        }
+    }
+};
+
+template <int RP, typename XT>
+__device__ __forceinline__ void prod_body(const ProdArgs &args, int bid)
+{
+    // A private copy: the grouped form would otherwise re-read the argument
+    // record after every direct-to-LDS load.
+    const ProdArgs a = args;
+    constexpr int NCB = RP / 16;
+    constexpr int NX = XOps<XT>::n;
+    constexpr int FT = 2 * kFP * RP * 64;             // split factor tile bytes (RP KB)
+    constexpr int FTK = FT / 1024;
+    constexpr int SFK = kTPS * FTK;                   // factor KB per step
+    constexpr int FOPS = (SFK + kWaves - 1) / kWaves; // factor KB per wave per step
+    constexpr int GOPS = 2 * kTPS * kBPW + FOPS;      // loads per wave per step
+    static_assert((kDepth - 1) * GOPS <= 63, "vmcnt range");
+    __shared__ __attribute__((aligned(1024))) signed char ring[kBufs][kTPS * FT];
+
+    const DevState *st = a.st;
+    if (a.sel != SEL_SLOT0 && st->done) return;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, lr = lane & 15;
+    const int kc = bid % a.nsplit;
+    const int64_t rb = bid / a.nsplit;
+    const int64_t kbeg = (int64_t)kc * a.kchunk;
+    int64_t kend = kbeg + a.kchunk;
+    if (kend > a.ld) kend = a.ld;
+    const int64_t row0 = rb * kBM + wave * kWM;
+    const int64_t ntile = a.ld / kKT;
+    // The wave's 16-row block b of tile t starts at ((row0/16 + b) ntile + t)
+    // 2 KB; this lane's 16 bytes of k-step s at s KB + 16 lane.
+    const signed char *zsrc = static_cast<const signed char *>(a.Z) +
+                              (row0 / 16) * ntile * 2048 + 16 * lane;
+    const int boff = (lr * 4 + fgroup(lr, g)) * 16;
+
+    floatx4 acc[kBPW][NCB];
+#pragma unroll
+    for (int b = 0; b < kBPW; ++b)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) acc[b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t t0 = kbeg / kKT, t1 = (kend + kKT - 1) / kKT;   // tiles [t0, t1)
+    const int64_t nstep = (t1 - t0 + kTPS - 1) / kTPS;            // kTPS tiles per step
+    if (t0 < t1) {
+        int32x4 z[kBufs][kTPS][kBPW][2];
+        // Issue group of step j (tiles clamped to [t0, t1)): this wave's share
+        // of the step's factor tiles into stage sg, then its Z fragments.
+        auto issue = [&](int64_t j, int sg, int32x4 (&zb)[kTPS][kBPW][2]) {
+#pragma unroll
+            for (int q = 0; q < FOPS; ++q) {
+                const int kb = (wave * FOPS + q < SFK) ? wave * FOPS + q : SFK - 1;
+                int64_t tile = t0 + kTPS * j + kb / FTK;
+                if (tile < t0) tile = t0;
+                if (tile > t1 - 1) tile = t1 - 1;
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(a.Fsl + tile * FT +
+                                                                     (kb % FTK) * 1024 + 16 * lane),
+                    (__attribute__((address_space(3))) void *)(ring[sg] + kb * 1024), 16, 0, 0);
+            }
+#pragma unroll
+            for (int h = 0; h < kTPS; ++h) {
+                int64_t tile = t0 + kTPS * j + h;
+                if (tile < t0) tile = t0;
+                if (tile > t1 - 1) tile = t1 - 1;
+#pragma unroll
+                for (int b = 0; b < kBPW; ++b) {
+                    const signed char *zp = zsrc + (b * ntile + tile) * 2048;
+#pragma unroll
+                    for (int s = 0; s < 2; ++s)
+                        zb[h][b][s] = __builtin_nontemporal_load(
+                            reinterpret_cast<const int32x4 *>(zp + s * 1024));
+                }
+            }
+        };
+        // The loop starts one round early (that round only issues the groups
+        // of steps 0 .. kDepth - 1), so that no load precedes it.
+        for (int64_t jb = -kBufs; jb < nstep; jb += kBufs) {
+            static_for<kBufs>([&](auto UU) {
+                constexpr int u = decltype(UU)::value;
+                constexpr int un = (u + kDepth) % kBufs;
+                const int64_t j = jb + u;
+                __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm((kDepth - 1) * GOPS));
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_sched_barrier(0);
+                issue(j + kDepth, un, z[un]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int h = 0; h < kTPS; ++h) {
+                    const int64_t t = t0 + kTPS * j + h;
+                    if (j >= 0 && t < t1) {                     // (uniform)
+                        const signed char *ft = ring[u] + h * FT;
+                        bf16x8 xs[kBPW][2][NX];
+#pragma unroll
+                        for (int b = 0; b < kBPW; ++b)
+#pragma unroll
+                            for (int s = 0; s < 2; ++s) XOps<XT>::get(z[u][h][b][s], xs[b][s]);
+#pragma unroll
+                        for (int s = 0; s < 2; ++s) {
+                            bf16x8 bp[NCB][kFP];
+#pragma unroll
+                            for (int c = 0; c < NCB; ++c)
+#pragma unroll
+                                for (int p = 0; p < kFP; ++p)
+                                    bp[c][p] = *reinterpret_cast<const bf16x8 *>(
+                                        ft + ((s * kFP + p) * RP + 16 * c) * 64 + boff);
+#pragma unroll
+                            for (int i = 0; i < NX; ++i)
+#pragma unroll
+                                for (int p = 0; p + i <= 1; ++p)
+#pragma unroll
+                                    for (int b = 0; b < kBPW; ++b)
+#pragma unroll
+                                        for (int c = 0; c < NCB; ++c)
+                                            acc[b][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                                xs[b][s][i], bp[c][p], acc[b][c], 0, 0, 0);
+                        }
+                    }
+                }
+            });
+        }
+        __builtin_amdgcn_s_waitcnt(0x0070);            // vmcnt(0): no load outlives the loop
+    }
+
+    // D layout: lane holds column lr of each block, rows 4g..4g+3.
+    double *Y = a.Y + (size_t)kc * a.rows_pad * RP;
+#pragma unroll
+    for (int b = 0; b < kBPW; ++b)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                Y[(row0 + 16 * b + 4 * g + i) * RP + c * 16 + lr] = (double)acc[b][c][i];
+}
+
+template <int RP>
+__global__ __launch_bounds__(256) void split_factor_kernel(ProdArgs a)
+{
+    split_body<RP>(a, blockIdx.x);
+}
+
+template <int RP, typename XT>
+__global__ __launch_bounds__(kWaves * 64, 1) void prod_x16_kernel(ProdArgs a)
+{
+    prod_body<RP, XT>(a, blockIdx.x);
+}
+
+template <int RP, typename XT>
+void launch(const ProdArgs &a, hipStream_t s, hipEvent_t mid)
+{
+    split_factor_kernel<RP><<<(unsigned)(a.ld / kKT), 256, 0, s>>>(a);
+    if (mid) (void)hipEventRecord(mid, s);
+    const int64_t blocks = (a.rows_pad / kBM) * a.nsplit;
+    prod_x16_kernel<RP, XT><<<(unsigned)blocks, kWaves * 64, 0, s>>>(a);
+}
+
+}  // namespace x16
+}  // namespace nmf

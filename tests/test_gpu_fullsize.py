@@ -99,3 +99,23 @@ def test_planted_16384_r64_exact_nnls(planted):
 def test_imagelike_10000x2000_r49(exact):
     p = S.imagelike(0)
     check_first_iteration(p, 3 if not exact else 1, 10, exact, EXACT if exact else BENCH)
+
+
+@pytest.mark.parametrize("xd", ["BF16", "F16"])
+def test_planted_16384_r64_16bit_x(planted, xd):
+    """The benchmark configuration with X stored in 16 bits (BF16 matrix-core
+    products): after 30 iterations the final error, evaluated in FP64 against
+    the FP32 X, is within 1e-3 absolute of the FP32 path's at the same
+    iteration (the FP32 path being the one checked against the oracle
+    above)."""
+    p = planted
+    kw = dict(max_iter=30, hp=3, inner_k=10, **BENCH)
+    print(f"case full-size {p.name} m={p.m} n={p.n} r={p.r} x_dtype={xd} {kw}", flush=True)
+    with P.Solver(p.X, p.r, x_dtype=P.XDtype[xd], prod=P.Prod.MFMA_FAST, **kw) as s:
+        a = s.solve(p.W0, p.H0)
+    with P.Solver(p.X, p.r, **kw) as s:
+        b = s.solve(p.W0, p.H0)
+    ra = residual(p.X, a.W, a.H)
+    rb = residual(p.X, b.W, b.H)
+    print(f"full-size {xd}: rho {ra:.6e} FP32 path {rb:.6e}", flush=True)
+    assert abs(ra - rb) < 1e-3
