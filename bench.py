@@ -37,8 +37,12 @@ HBM_PEAK_GBS = 8000.0
 # Sources of the exact-integer product kernel (the dominant kernel of the
 # default workload): the committed traffic figures apply while they are
 # unchanged.
-PRODUCT_SOURCES = ["paper_1805_06604_amd/csrc/prod_i8.h",
-                   "paper_1805_06604_amd/csrc/prod_i8.hip"]
+# Sources of the product kernel a workload's traffic summary was taken on:
+# the exact-integer product (FP32 X) and the 16-bit X product.
+PRODUCT_SOURCES = {"i8": ["paper_1805_06604_amd/csrc/prod_i8.h",
+                          "paper_1805_06604_amd/csrc/prod_i8.hip"],
+                   "x16": ["paper_1805_06604_amd/csrc/prod_x16.h",
+                           "paper_1805_06604_amd/csrc/prod_x16.hip"]}
 XBYTES = {"f32": 4, "bf16": 2, "f16": 2}
 
 
@@ -81,15 +85,15 @@ def parse():
     return ap.parse_args()
 
 
-def source_digest():
+def source_digest(kind="i8"):
     h = hashlib.sha256()
-    for rel in PRODUCT_SOURCES:
+    for rel in PRODUCT_SOURCES[kind]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_key):
+def measured_traffic(workload_key, kind="i8"):
     """HBM bytes per product launch from the committed counter summary, if it
     was taken on the current product kernel source for this workload."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -97,7 +101,7 @@ def measured_traffic(workload_key):
         return None
     with open(path) as f:
         rec = json.load(f).get(workload_key)
-    if not rec or rec.get("source_sha") != source_digest():
+    if not rec or rec.get("source_sha") != source_digest(kind):
         return None
     return rec.get("bytes_per_launch")
 
@@ -240,7 +244,9 @@ def variant(args, P, S, p, stream, torch, x_dtype, prod, K, steps, label):
         "value": 1e3 / ms, "unit": "iters/s", "ms_per_step": ms, "steps": steps, "phase_ms": ph,
         "rho_final": float(res.trace[-1]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"planted_{m}x{n}_r{r}_{x_dtype}_{prod}",
+                                                 "i8" if x_dtype == "f32" else "x16"),
                      "kernel": "X-streaming product", "bytes_per_launch": 0.5 * nbytes,
                      "ms_per_launch": 0.5 * (ph["prod_ct"] + ph["prod_a"])}}
 
@@ -360,7 +366,7 @@ def main():
     achieved = (bytes_ct + bytes_a) / ((phases["prod_ct"] + phases["prod_a"]) * 1e-3) / 1e9
     iter_bytes = 2 * m * n * sx + 7 * (m + n) * r * 4
     key = f"planted_{m}x{n}_r{r}_{args.x_dtype}_{args.prod}"
-    traffic = measured_traffic(key)
+    traffic = measured_traffic(key, "i8" if args.x_dtype == "f32" else "x16")
     out = {
         "metric": METRIC,
         "value": args.steps / (ms * 1e-3),
