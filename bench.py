@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--copy-calib", action="store_true",
                     help="run the 1 GiB reference copy (counter calibration) first")
-    ap.add_argument("--serve-requests", type=int, default=128,
+    ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the batched-serving measurement (0 disables)")
     ap.add_argument("--serve-qps", type=float, default=2000.0,
                     help="Poisson arrival rate of the serving stream")
