@@ -250,8 +250,10 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
     double xa[NS];             // x in A layout (sweep modes)
     if constexpr (MI::sweeps) {
         // B operands: -G(4s+g, 16b+lr); inverse diagonal of coordinate 16b+lr;
-        // strictly lower in-block Gram entries, tri[b][q][l] = G(16b+l, 16b+q)
-        // for l > q (0 otherwise), for the in-block corrections.
+        // strictly lower in-block Gram entries scaled by the inverse diagonal
+        // of their row, tri[b][q][l] = G(16b+l, 16b+q) / G(16b+l, 16b+l) for
+        // l > q (0 otherwise, and 0 for a zero diagonal), for the in-block
+        // corrections of the scaled numerators.
         // B operands in LDS (shared by the four waves, read right before each
         // MFMA): s_gb[s][b][lane] = -G(4s+g, 16b+lr).
         double inv[NB];
@@ -264,7 +266,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
         for (int b = 0; b < NB; ++b) inv[b] = G[RP * RP + 16 * b + lr];
         for (int e = tid; e < NB * 256; e += kThreads) {
             const int b = e >> 8, q = (e >> 4) & 15, l = e & 15;
-            s_tri[b][q][l] = (l > q) ? G[(16 * b + l) * RP + 16 * b + q] : 0.0;
+            s_tri[b][q][l] = (l > q) ? G[(16 * b + l) * RP + 16 * b + q] * G[RP * RP + 16 * b + l] : 0.0;
         }
         // x in A layout: row lr, coordinate 4s+g.
         {
@@ -302,11 +304,15 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                     if (s & 1) tn1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], bo, tn1, 0, 0, 0);
                     else tn0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], bo, tn0, 0, 0, 0);
                 }
+                // The numerators scaled by the inverse diagonal, tau = t / G_kk
+                // (the step of the closed form before projection).
                 double4v t = tcur;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) t[v] *= inv[b];
                 // Coordinates 16b .. 16b+15 in order. Every lane forms the
                 // change its coordinate would take; lane q's is the one used
-                // at step q, and the later coordinates correct their t. Lanes
-                // l <= q get a zero correction, so each t stops at the value
+                // at step q, and the later coordinates correct their tau. Lanes
+                // l <= q get a zero correction, so each tau stops at the value
                 // its own step used. Coordinates at or beyond r (rank padding,
                 // only ever in the last block) have x = 0, a zero inverse
                 // diagonal and hence no change: their steps are skipped (a
@@ -317,14 +323,11 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                         const double gq = s_tri[b][q][lr];
                         // Stage by stage over the four independent rows of
                         // the lane, so that their latencies overlap.
-                        // The change max(x + t/G_kk, 0) - x, formed as
-                        // max(t/G_kk, -x): equal up to rounding, one step
-                        // shorter.
+                        // The change max(x + tau, 0) - x, formed as
+                        // max(tau, -x): equal up to rounding, shorter.
                         double d[4];
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) d[v] = t[v] * inv[b];
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) d[v] = fmax(d[v], -xd[b][v]);
+                        for (int v = 0; v < 4; ++v) d[v] = fmax(t[v], -xd[b][v]);
 #pragma unroll
                         for (int v = 0; v < 4; ++v) d[v] = row_bcast<q>(d[v]);
 #pragma unroll
@@ -332,7 +335,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                     }
                 });
 #pragma unroll
-                for (int v = 0; v < 4; ++v) xd[b][v] = fmax(fma(t[v], inv[b], xd[b][v]), 0.0);
+                for (int v = 0; v < 4; ++v) xd[b][v] = fmax(xd[b][v] + t[v], 0.0);
                 // The block's new values into A layout (wave-private LDS tile;
                 // the LDS operations of a wave complete in order).
 #pragma unroll
