@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--serve-seq", type=int, default=16,
                     help="requests of the same stream solved one at a time (baseline)")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-chunk", type=int, default=10,
+                    help="batch iterations between completion checks")
     ap.add_argument("--serve-qps-low", type=float, default=100.0,
                     help="second arrival rate, below saturation (0: skip)")
     ap.add_argument("--x16-steps", type=int, default=50,
@@ -266,7 +268,8 @@ def serving(args, P, S, qps, n_seq):
               inner_k=args.inner_k)
     lat = [None] * len(reqs)
     iters = []
-    with P.Batch(int(args.serve_budget_gb * (1 << 30)), max_active=512, check_every=10) as B:
+    with P.Batch(int(args.serve_budget_gb * (1 << 30)), max_active=512,
+                 check_every=args.serve_chunk) as B:
         tickets = {}
         nxt = 0
         t0 = time.perf_counter()
@@ -276,7 +279,7 @@ def serving(args, P, S, qps, n_seq):
                 p = probs[nxt]
                 tickets[nxt] = B.submit(p.X, p.r, p.W0, p.H0, **kw)
                 nxt += 1
-            a, q, d = B.step(10)
+            a, q, d = B.step(args.serve_chunk)
             for i in list(tickets):
                 g = B.result(tickets[i])
                 if g is not None:

@@ -265,8 +265,10 @@ nmf_status nmf_batch_submit(nmf_batch *b, const nmf_matrix *X, const nmf_params 
 /* Admits queued problems in submission order while the arena and max_active
  * allow, runs `iters` batch iterations (check_every at a time, retiring the
  * problems that stopped after each check; a retired problem's result is kept
- * on the host), and returns the numbers of active, queued and retired-unread
- * problems (each pointer nullable). Blocks until the device work is done.
+ * on the host), and returns the numbers of active (admitted ones included),
+ * queued and retired-unread problems (each pointer nullable). The set-up of
+ * problems admitted while a chunk runs overlaps it; they join at the next
+ * chunk. Blocks until the device work is done.
  * Errors: NMF_E_INVAL (iters < 1), NMF_E_DEVICE. */
 nmf_status nmf_batch_step(nmf_batch *b, int32_t iters, int32_t *active, int32_t *queued,
                           int32_t *retired);

@@ -196,6 +196,7 @@ struct nmf_batch {
     char *pool = nullptr;
     Arena arena;
     std::deque<Prob *> queue;
+    std::vector<Prob *> pending;         // admitted (set-up enqueued), not yet in the tables
     std::vector<Prob *> active;
     std::map<int64_t, std::unique_ptr<Prob>> all;
     int64_t next_ticket = 1;
@@ -458,6 +459,43 @@ nmf_status retire(nmf_batch *B)
     return NMF_OK;
 }
 
+// Admits queued problems in submission order while the arena and max_active
+// allow, enqueueing their set-up on the batch stream (see admit).
+nmf_status admit_queued(nmf_batch *B)
+{
+    while (!B->queue.empty() &&
+           (int)(B->active.size() + B->pending.size()) < B->bp.max_active) {
+        Prob *q = B->queue.front();
+        nmf_status err;
+        if (!admit(B, *q, &err)) {
+            if (err != NMF_OK) return err;
+            break;
+        }
+        B->queue.pop_front();
+        B->pending.push_back(q);
+    }
+    return NMF_OK;
+}
+
+// Waits for the set-up of the pending problems, frees their temporaries and
+// host copies, and moves them to the active set (the tables then need a
+// rebuild).
+nmf_status finish_admissions(nmf_batch *B)
+{
+    BHIP(hipStreamSynchronize(B->s));
+    for (Prob *q : B->pending) {
+        B->arena.release(q->toff, q->tbytes);
+        q->has_tmp = false;
+        std::vector<float>().swap(q->X);
+        std::vector<float>().swap(q->W0);
+        std::vector<float>().swap(q->H0);
+        B->active.push_back(q);
+    }
+    B->pending.clear();
+    B->dirty = true;
+    return NMF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -557,33 +595,16 @@ nmf_status nmf_batch_step(nmf_batch *B, int32_t iters, int32_t *active, int32_t 
     BHIP(hipSetDevice(B->device));
     int done_iters = 0;
     while (done_iters < iters) {
-        // Admission in submission order.
-        std::vector<Prob *> admitted;
-        while (!B->queue.empty() && (int)B->active.size() < B->bp.max_active) {
-            Prob *q = B->queue.front();
-            nmf_status err;
-            if (!admit(B, *q, &err)) {
-                if (err != NMF_OK) return err;
-                break;
-            }
-            B->queue.pop_front();
-            B->active.push_back(q);
-            admitted.push_back(q);
-            B->dirty = true;
+        if (B->active.empty() && B->pending.empty()) {
+            nmf_status st = admit_queued(B);
+            if (st != NMF_OK) return st;
         }
-        if (!admitted.empty()) {
-            BHIP(hipStreamSynchronize(B->s));
-            for (Prob *q : admitted) {
-                B->arena.release(q->toff, q->tbytes);
-                q->has_tmp = false;
-                std::vector<float>().swap(q->X);
-                std::vector<float>().swap(q->W0);
-                std::vector<float>().swap(q->H0);
-            }
+        if (!B->pending.empty()) {
+            nmf_status st = finish_admissions(B);
+            if (st != NMF_OK) return st;
         }
         if (B->active.empty()) break;
         if (B->dirty) {
-            BHIP(hipStreamSynchronize(B->s));
             nmf_status st = rebuild(B);
             if (st != NMF_OK) return st;
         }
@@ -591,10 +612,14 @@ nmf_status nmf_batch_step(nmf_batch *B, int32_t iters, int32_t *active, int32_t 
         nmf_status st = run_iterations(B, chunk);
         if (st != NMF_OK) return st;
         done_iters += chunk;
+        // The set-up of the next problems (uploads, slicing, e(0)) runs on the
+        // batch stream while the class streams run the chunk just enqueued.
+        st = admit_queued(B);
+        if (st != NMF_OK) return st;
         st = retire(B);
         if (st != NMF_OK) return st;
     }
-    if (active) *active = (int32_t)B->active.size();
+    if (active) *active = (int32_t)(B->active.size() + B->pending.size());
     if (queued) *queued = (int32_t)B->queue.size();
     if (retired) *retired = B->retired_unread;
     return NMF_OK;
