@@ -268,6 +268,7 @@ def serving(args, P, S, qps, n_seq):
               inner_k=args.inner_k)
     lat = [None] * len(reqs)
     iters = []
+    host = {"submit": 0.0, "step": 0.0, "result": 0.0}
     with P.Batch(int(args.serve_budget_gb * (1 << 30)), max_active=512,
                  check_every=args.serve_chunk) as B:
         tickets = {}
@@ -277,15 +278,25 @@ def serving(args, P, S, qps, n_seq):
             now = time.perf_counter() - t0
             while nxt < len(reqs) and reqs[nxt].t_arrive <= now:
                 p = probs[nxt]
+                h0 = time.perf_counter()
                 tickets[nxt] = B.submit(p.X, p.r, p.W0, p.H0, **kw)
+                host["submit"] += time.perf_counter() - h0
                 nxt += 1
+            h0 = time.perf_counter()
             a, q, d = B.step(args.serve_chunk)
+            h1 = time.perf_counter()
+            host["step"] += h1 - h0
+            # d results are waiting: collect them (oldest tickets first).
             for i in list(tickets):
+                if d == 0:
+                    break
                 g = B.result(tickets[i])
                 if g is not None:
                     lat[i] = time.perf_counter() - t0 - reqs[i].t_arrive
                     iters.append(g.n_iter)
                     del tickets[i]
+                    d -= 1
+            host["result"] += time.perf_counter() - h1
             if nxt == len(reqs) and not tickets:
                 break
             if not tickets and nxt < len(reqs):
@@ -299,6 +310,7 @@ def serving(args, P, S, qps, n_seq):
         "solves_per_s": len(reqs) / span, "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)), "max_ms": float(lat_ms[-1]),
         "mean_iters": float(np.mean(iters)), "generation_s": t_gen,
+        "host_s": host,
     }
     n_seq = min(n_seq, len(reqs))
     if n_seq > 0:
