@@ -19,12 +19,13 @@
 // that each factor operand read from LDS serves 32 rows). A workgroup is 8
 // waves (two per SIMD) over 256 rows x RP columns and one K-chunk; each wave
 // owns two 16-row blocks and all RP/16 column blocks, streams its Z fragments
-// straight into
-// registers three tiles ahead with non-temporal loads, and reads the split
-// factor tile from a 4-stage LDS ring filled by direct global-to-LDS loads in
-// the same issue group; one barrier per tile. The K loop is unrolled by the
-// four buffers and every load is issued unconditionally (tile index clamped
-// to the K-chunk), so the wait counts are static.
+// straight into registers three steps (of kTPS tiles) ahead with non-temporal
+// loads, and reads the split factor tiles from a 4-stage LDS ring filled by
+// direct global-to-LDS loads in the same issue group; one barrier per step.
+// The K loop is unrolled by the four buffers and every load is issued
+// unconditionally (tile index clamped to the K-chunk: the loop starts one
+// round early and ends past the last tile with harmless reloads), so the wait
+// counts are static and no load precedes the loop.
 #pragma once
 
 #include "nmf_internal.h"
