@@ -76,6 +76,10 @@ def parse():
                     help="second arrival rate, below saturation (0: skip)")
     ap.add_argument("--x16-steps", type=int, default=50,
                     help="timed steps of the 16-bit X runs (BF16, FP16; 0: skip)")
+    ap.add_argument("--workload-steps", type=int, default=50,
+                    help="timed iterations on each of the other configurations (0: skip)")
+    ap.add_argument("--workload-oracle", type=int, default=1,
+                    help="1: also time the oracle on a few iterations of each")
     ap.add_argument("--k1-steps", type=int, default=50,
                     help="timed steps of the run with one inner sweep (0: skip)")
     ap.add_argument("--eanls-steps", type=int, default=20,
@@ -253,6 +257,53 @@ def variant(args, P, S, p, stream, torch, x_dtype, prod, K, steps, label):
                      "ms_per_launch": 0.5 * (ph["prod_ct"] + ph["prod_a"])}}
 
 
+def workloads(args, P, S, stream, torch):
+    """The other configurations of the measurement plan, each as its own
+    seeded synthetic stand-in (low-rank and full-rank synthetic sets, image-
+    like dense, document-like CSR): GPU iterations/s with the effective bytes
+    per second of the two X passes, beside the FP64 oracle's iterations/s on
+    a bounded number of iterations (single thread)."""
+    import oracle
+    kw = dict(hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01, eta=1.5, inner_k=10)
+    specs = [("C1 low-rank synthetic 200x200 r=10", lambda: S.lowrank(0), 100),
+             ("E2 full-rank synthetic 200x200 r=20", lambda: S.fullrank(0), 100),
+             ("C2 image-like dense 10000x2000 r=49", lambda: S.imagelike(0), 2),
+             ("C3 document-like CSR 30000x20000 r=20, nnz 1.8M", lambda: S.doclike(0), 1)]
+    out = {}
+    for name, make, oracle_iters in specs:
+        p = make()
+        steps, warm = args.workload_steps, 10
+        with P.Solver(p.X, p.r, max_iter=warm + steps, **kw) as sv:
+            sv.start(p.W0, p.H0, stream=stream)
+            sv.iterate(warm, stream=stream)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            sv.iterate(steps, stream=stream)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / steps
+            res = sv.read(stream=stream)
+        m, n, r = p.m, p.n, p.r
+        if isinstance(p.X, S.Csr):
+            # values and column indices of the CSR and CSC copies, and their row pointers
+            xbytes = 2 * p.X.val.size * 8 + (m + n + 2) * 8
+        else:
+            xbytes = 2 * m * n * 4
+        it_bytes = xbytes + 7 * (m + n) * r * 4
+        rec = {"iters_per_s": 1e3 / ms, "ms_per_iter": ms, "steps": steps,
+               "effective_gbs": it_bytes / (ms * 1e-3) / 1e9, "rho_final": float(res.trace[-1])}
+        if args.workload_oracle:
+            t0 = time.perf_counter()
+            oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=oracle_iters, **kw)
+            t = time.perf_counter() - t0
+            rec["oracle"] = {"iters_per_s": oracle_iters / t, "iters": oracle_iters, "seconds": t,
+                             "cores": 1, "kind": "oracle"}
+        out[name] = rec
+    return out
+
+
 def serving(args, P, S, qps, n_seq):
     """Batched solves of a Poisson stream of small problems (m, n ~
     U{64..2048}, r in {5, 10, 20, 40}, X = max(0, W H + 1% noise)), each run
@@ -428,6 +479,8 @@ def main():
         out["eanls"] = ea
     if ad is not None:
         out["adaptive_inner"] = ad
+    if args.workload_steps > 0:
+        out["workloads"] = workloads(args, P, S, stream, torch)
     if args.serve_requests > 0:
         out["serving"] = serving(args, P, S, args.serve_qps, args.serve_seq)
         if args.serve_qps_low > 0:
