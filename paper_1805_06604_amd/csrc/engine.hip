@@ -286,38 +286,54 @@ nmf_status upload_dense(nmf_ctx *c, const nmf_matrix *X)
     if (nx2) (void)hipFree(nx2);
     if (e != hipSuccess)
         return fail(c, NMF_E_DEVICE, "uploading X failed: %s", hipGetErrorString(e));
-    if (c->prod_kernel == nmf::PK_MFMA_I8) {
-        // Keep only the int8 slices of X and X^T (4 bytes per entry).
+    // Replaces X and X^T by the copies the product streams, made by `fill`
+    // into new buffers of xs_bytes and xts_bytes; the new buffers are freed
+    // again if any step fails.
+    auto replace_x = [&](size_t xs_bytes, size_t xts_bytes, auto fill) -> nmf_status {
         void *xs = nullptr, *xts = nullptr;
-        HIP_TRY(c, hipMalloc(&xs, (size_t)c->b.m_pad * c->ldx * 4));
-        HIP_TRY(c, hipMalloc(&xts, (size_t)c->b.n_pad * c->ldxt * 4));
-        HIP_TRY(c, hipMemsetAsync(xs, 0, (size_t)c->b.m_pad * c->ldx * 4, c->own));
-        HIP_TRY(c, hipMemsetAsync(xts, 0, (size_t)c->b.n_pad * c->ldxt * 4, c->own));
-        HIP_TRY(c, dalloc(&c->zexp_x, (size_t)c->b.m_pad));
-        HIP_TRY(c, dalloc(&c->zexp_xt, (size_t)c->b.n_pad));
-        HIP_TRY(c, hipMemsetAsync(c->zexp_x, 0, sizeof(int) * c->b.m_pad, c->own));
-        HIP_TRY(c, hipMemsetAsync(c->zexp_xt, 0, sizeof(int) * c->b.n_pad, c->own));
-        HIP_TRY(c, nmf::i8::slice_rows(c->X, xd, c->m, c->n, c->ldx, c->ldx, xs, c->zexp_x, c->own));
-        HIP_TRY(c, nmf::i8::slice_rows(c->Xt, xd, c->n, c->m, c->ldxt, c->ldxt, xts, c->zexp_xt,
-                                       c->own));
-        HIP_TRY(c, hipStreamSynchronize(c->own));
+        hipError_t e2 = hipMalloc(&xs, xs_bytes);
+        if (e2 == hipSuccess) e2 = hipMalloc(&xts, xts_bytes);
+        if (e2 == hipSuccess) e2 = fill(xs, xts);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->own);
+        if (e2 != hipSuccess) {
+            if (xs) (void)hipFree(xs);
+            if (xts) (void)hipFree(xts);
+            return fail(c, NMF_E_DEVICE, "preparing X for the product failed: %s",
+                        hipGetErrorString(e2));
+        }
         (void)hipFree(c->X);
         (void)hipFree(c->Xt);
         c->X = xs;
         c->Xt = xts;
+        return NMF_OK;
+    };
+    if (c->prod_kernel == nmf::PK_MFMA_I8) {
+        // Keep only the int8 slices of X and X^T (4 bytes per entry).
+        HIP_TRY(c, dalloc(&c->zexp_x, (size_t)c->b.m_pad));
+        HIP_TRY(c, dalloc(&c->zexp_xt, (size_t)c->b.n_pad));
+        HIP_TRY(c, hipMemsetAsync(c->zexp_x, 0, sizeof(int) * c->b.m_pad, c->own));
+        HIP_TRY(c, hipMemsetAsync(c->zexp_xt, 0, sizeof(int) * c->b.n_pad, c->own));
+        const size_t sb = (size_t)c->b.m_pad * c->ldx * 4, stb = (size_t)c->b.n_pad * c->ldxt * 4;
+        const nmf_status st = replace_x(sb, stb, [&](void *xs, void *xts) {
+            hipError_t e3 = hipMemsetAsync(xs, 0, sb, c->own);
+            if (e3 == hipSuccess) e3 = hipMemsetAsync(xts, 0, stb, c->own);
+            if (e3 == hipSuccess)
+                e3 = nmf::i8::slice_rows(c->X, xd, c->m, c->n, c->ldx, c->ldx, xs, c->zexp_x, c->own);
+            if (e3 == hipSuccess)
+                e3 = nmf::i8::slice_rows(c->Xt, xd, c->n, c->m, c->ldxt, c->ldxt, xts, c->zexp_xt,
+                                         c->own);
+            return e3;
+        });
+        if (st != NMF_OK) return st;
     }
     if (c->prod_kernel == nmf::PK_MFMA_X16) {
         // Keep X and X^T in 16 bits, in the fragment order the product streams.
-        void *xf = nullptr, *xtf = nullptr;
-        HIP_TRY(c, hipMalloc(&xf, xsz));
-        HIP_TRY(c, hipMalloc(&xtf, xtsz));
-        HIP_TRY(c, nmf::x16::to_fragments(c->X, c->b.m_pad, c->ldx, xf, c->own));
-        HIP_TRY(c, nmf::x16::to_fragments(c->Xt, c->b.n_pad, c->ldxt, xtf, c->own));
-        HIP_TRY(c, hipStreamSynchronize(c->own));
-        (void)hipFree(c->X);
-        (void)hipFree(c->Xt);
-        c->X = xf;
-        c->Xt = xtf;
+        const nmf_status st = replace_x(xsz, xtsz, [&](void *xf, void *xtf) {
+            hipError_t e3 = nmf::x16::to_fragments(c->X, c->b.m_pad, c->ldx, xf, c->own);
+            if (e3 == hipSuccess) e3 = nmf::x16::to_fragments(c->Xt, c->b.n_pad, c->ldxt, xtf, c->own);
+            return e3;
+        });
+        if (st != NMF_OK) return st;
     }
     return NMF_OK;
 }
