@@ -139,11 +139,22 @@ def cpu_baseline(args):
                     break
     except OSError:
         pass
-    return {"value": 1.0 / per_iter_full, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 oracle (single thread), {args.cpu_iters} iterations of the planted "
-                       f"workload at {s}x{s}, r={args.r}, K={args.inner_k} took {t:.2f} s; scaled "
-                       f"to {args.m}x{args.n} by the flop ratio {scale:.1f}; host {cpu}, "
-                       f"os.cpu_count()={os.cpu_count()}")}
+    out = {"value": 1.0 / per_iter_full, "unit": "iters/s", "cores": 1, "kind": "oracle",
+           "sample": (f"FP64 oracle (single thread), {args.cpu_iters} iterations of the planted "
+                      f"workload at {s}x{s}, r={args.r}, K={args.inner_k} took {t:.2f} s; scaled "
+                      f"to {args.m}x{args.n} by the flop ratio {scale:.1f}; host {cpu}, "
+                      f"os.cpu_count()={os.cpu_count()}")}
+    if args.workload_oracle and args.workload_steps > 0:
+        # The oracle on the same problems as the workloads leg, a few iterations each.
+        cfg = {}
+        for name, make, iters in workload_specs(S):
+            p = make()
+            t0 = time.perf_counter()
+            oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=iters, **WORKLOAD_PARAMS)
+            t = time.perf_counter() - t0
+            cfg[name] = {"iters_per_s": iters / t, "iters": iters, "seconds": t}
+        out["workloads"] = cfg
+    return out
 
 
 FP64_VECTOR_PEAK_TFS = 78.6
@@ -261,16 +272,11 @@ def workloads(args, P, S, stream, torch):
     """The other configurations of the measurement plan, each as its own
     seeded synthetic stand-in (low-rank and full-rank synthetic sets, image-
     like dense, document-like CSR): GPU iterations/s with the effective bytes
-    per second of the two X passes, beside the FP64 oracle's iterations/s on
-    a bounded number of iterations (single thread)."""
-    import oracle
-    kw = dict(hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01, eta=1.5, inner_k=10)
-    specs = [("C1 low-rank synthetic 200x200 r=10", lambda: S.lowrank(0), 100),
-             ("E2 full-rank synthetic 200x200 r=20", lambda: S.fullrank(0), 100),
-             ("C2 image-like dense 10000x2000 r=49", lambda: S.imagelike(0), 2),
-             ("C3 document-like CSR 30000x20000 r=20, nnz 1.8M", lambda: S.doclike(0), 1)]
+    per second of the iteration (the oracle's rates on the same problems are
+    in the cpu_baseline leg)."""
+    kw = WORKLOAD_PARAMS
     out = {}
-    for name, make, oracle_iters in specs:
+    for name, make, _ in workload_specs(S):
         p = make()
         steps, warm = args.workload_steps, 10
         with P.Solver(p.X, p.r, max_iter=warm + steps, **kw) as sv:
@@ -292,16 +298,21 @@ def workloads(args, P, S, stream, torch):
         else:
             xbytes = 2 * m * n * 4
         it_bytes = xbytes + 7 * (m + n) * r * 4
-        rec = {"iters_per_s": 1e3 / ms, "ms_per_iter": ms, "steps": steps,
-               "effective_gbs": it_bytes / (ms * 1e-3) / 1e9, "rho_final": float(res.trace[-1])}
-        if args.workload_oracle:
-            t0 = time.perf_counter()
-            oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=oracle_iters, **kw)
-            t = time.perf_counter() - t0
-            rec["oracle"] = {"iters_per_s": oracle_iters / t, "iters": oracle_iters, "seconds": t,
-                             "cores": 1, "kind": "oracle"}
-        out[name] = rec
+        out[name] = {"iters_per_s": 1e3 / ms, "ms_per_iter": ms, "steps": steps,
+                     "effective_gbs": it_bytes / (ms * 1e-3) / 1e9,
+                     "rho_final": float(res.trace[-1])}
     return out
+
+
+# The other configurations: (name, generator, oracle iterations timed).
+WORKLOAD_PARAMS = dict(hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01, eta=1.5, inner_k=10)
+
+
+def workload_specs(S):
+    return [("C1 low-rank synthetic 200x200 r=10", lambda: S.lowrank(0), 100),
+            ("E2 full-rank synthetic 200x200 r=20", lambda: S.fullrank(0), 100),
+            ("C2 image-like dense 10000x2000 r=49", lambda: S.imagelike(0), 2),
+            ("C3 document-like CSR 30000x20000 r=20, nnz 1.8M", lambda: S.doclike(0), 1)]
 
 
 def serving(args, P, S, qps, n_seq):
