@@ -92,7 +92,8 @@ struct Prob {
     int64_t m = 0, n = 0;
     int r = 0, rp = 0;
     int64_t m_pad = 0, n_pad = 0, ldx = 0, ldxt = 0;
-    std::vector<float> X, W0, H0;      // inputs until admitted
+    std::unique_ptr<float[]> X;        // inputs until admitted
+    std::vector<float> W0, H0;
     size_t off = 0, bytes = 0;         // persistent block
     size_t toff = 0, tbytes = 0;       // admission temporaries
     bool has_tmp = false;
@@ -270,7 +271,7 @@ bool admit(nmf_batch *B, Prob &q, nmf_status *err)
     if (e == hipSuccess) e = hipMemsetAsync(B->arena.base + toff, 0, tneed, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b.st, &h, sizeof(h), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(q.src, q.X.data(), sizeof(float) * q.m * q.n, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(q.src, q.X.get(), sizeof(float) * q.m * q.n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b.stage, q.W0.data(), sizeof(float) * q.m * q.r, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -486,7 +487,7 @@ nmf_status finish_admissions(nmf_batch *B)
     for (Prob *q : B->pending) {
         B->arena.release(q->toff, q->tbytes);
         q->has_tmp = false;
-        std::vector<float>().swap(q->X);
+        q->X.reset();
         std::vector<float>().swap(q->W0);
         std::vector<float>().swap(q->H0);
         B->active.push_back(q);
@@ -542,7 +543,7 @@ nmf_status nmf_batch_submit(nmf_batch *B, const nmf_matrix *X, const nmf_params 
     if (!B || !ticket) return berr(NMF_E_INVAL, "batch and ticket must not be NULL");
     nmf_status st = nmf::host::check_params(p);
     if (st != NMF_OK) return st;
-    st = nmf::host::check_matrix(X);
+    st = nmf::host::check_matrix_shape(X);     // the values are checked while copied below
     if (st != NMF_OK) return st;
     if (X->fmt != NMF_DENSE_ROWMAJOR)
         return berr(NMF_E_UNSUPPORTED, "batched solves take dense X");
@@ -553,9 +554,6 @@ nmf_status nmf_batch_submit(nmf_batch *B, const nmf_matrix *X, const nmf_params 
     if (!W0 || !H0) return berr(NMF_E_INVAL, "W0 and H0 must not be NULL");
     const int64_t m = X->m, n = X->n;
     const int r = p->r;
-    bool nonzero = false;
-    for (int64_t i = 0; i < m * n && !nonzero; ++i) nonzero = X->dense[i] != 0.0f;
-    if (!nonzero) return berr(NMF_E_INVAL, "X is zero: the relative error is undefined");
     for (int64_t i = 0; i < m * r; ++i)
         if (!(W0[i] >= 0.0f) || !std::isfinite(W0[i]))
             return berr(NMF_E_INVAL, "W0 has a negative or non-finite entry");
@@ -577,7 +575,13 @@ nmf_status nmf_batch_submit(nmf_batch *B, const nmf_matrix *X, const nmf_params 
     nmf::host::plan_product(q->pc, nmf::PK_MFMA_I8, n, q->n_pad, m, q->ldxt, kBatchTargetWG);
     if (layout(*q, nullptr) + layout_tmp(*q, nullptr) > (size_t)B->bp.hbm_budget)
         return berr(NMF_E_NOMEM, "the problem alone exceeds the batch arena");
-    q->X.assign(X->dense, X->dense + m * n);
+    q->X.reset(new (std::nothrow) float[(size_t)(m * n)]);
+    if (!q->X) return berr(NMF_E_NOMEM, "host allocation failed");
+    bool nonzero = false;
+    const int64_t bad = nmf::host::copy_checked(X->dense, q->X.get(), m * n, &nonzero);
+    if (bad >= 0)
+        return berr(NMF_E_INVAL, "X has a non-finite entry at " + std::to_string(bad));
+    if (!nonzero) return berr(NMF_E_INVAL, "X is zero: the relative error is undefined");
     q->W0.assign(W0, W0 + m * r);
     q->H0.assign(H0, H0 + (int64_t)r * n);
     q->ticket = B->next_ticket++;

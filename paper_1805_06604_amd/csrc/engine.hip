@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <thread>
 #include <new>
 #include <string>
 #include <vector>
@@ -147,7 +148,77 @@ nmf_status check_params(const nmf_params *p)
     return NMF_OK;
 }
 
-nmf_status check_matrix(const nmf_matrix *X)
+// Index of the first non-finite value of v[0..cnt), or -1. Blocks are scanned
+// without an exit inside (so the scan vectorizes); only a block that holds a
+// non-finite value is searched again.
+int64_t first_nonfinite(const float *v, int64_t cnt)
+{
+    constexpr int64_t kBlock = 4096;
+    for (int64_t b = 0; b < cnt; b += kBlock) {
+        const int64_t e = std::min(cnt, b + kBlock);
+        uint32_t bad = 0;
+        for (int64_t i = b; i < e; ++i) {
+            uint32_t u;
+            std::memcpy(&u, v + i, sizeof(u));
+            bad |= (uint32_t)((u & 0x7f800000u) == 0x7f800000u);   // exponent all ones: inf or NaN
+        }
+        if (bad)
+            for (int64_t i = b; i < e; ++i)
+                if (!std::isfinite(v[i])) return i;
+    }
+    return -1;
+}
+
+int64_t copy_checked_serial(const float *src, float *dst, int64_t cnt, bool *nonzero)
+{
+    constexpr int64_t kBlock = 4096;
+    uint32_t any = 0;
+    for (int64_t b = 0; b < cnt; b += kBlock) {
+        const int64_t e = std::min(cnt, b + kBlock);
+        uint32_t bad = 0;
+        for (int64_t i = b; i < e; ++i) {
+            uint32_t u;
+            std::memcpy(&u, src + i, sizeof(u));
+            std::memcpy(dst + i, &u, sizeof(u));
+            bad |= (uint32_t)((u & 0x7f800000u) == 0x7f800000u);
+            any |= u & 0x7fffffffu;
+        }
+        if (bad) return first_nonfinite(src + b, e - b) + b;
+    }
+    *nonzero = any != 0;
+    return -1;
+}
+
+// copy_checked_serial over up to 4 threads for large arrays (one host core
+// copies far below the memory bandwidth).
+int64_t copy_checked(const float *src, float *dst, int64_t cnt, bool *nonzero)
+{
+    constexpr int64_t kPerThread = int64_t(1) << 18;     // 1 MB of floats
+    const int nt = (int)std::min<int64_t>(4, cnt / kPerThread);
+    if (nt < 2) return copy_checked_serial(src, dst, cnt, nonzero);
+    const int64_t chunk = (cnt + nt - 1) / nt;
+    int64_t bad[4] = {-1, -1, -1, -1};
+    bool nz[4] = {false, false, false, false};
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) {
+        const int64_t b = t * chunk, e = std::min(cnt, b + chunk);
+        th.emplace_back([=, &bad, &nz] {
+            const int64_t i = copy_checked_serial(src + b, dst + b, e - b, &nz[t]);
+            bad[t] = i < 0 ? -1 : b + i;
+        });
+    }
+    bad[0] = copy_checked_serial(src, dst, std::min(cnt, chunk), &nz[0]);
+    for (auto &x : th) x.join();
+    bool any = false;
+    for (int t = 0; t < nt; ++t) {
+        if (bad[t] >= 0) return bad[t];                    // the first slice with one
+        any = any || nz[t];
+    }
+    *nonzero = any;
+    return -1;
+}
+
+nmf_status check_matrix(const nmf_matrix *X, bool scan_dense = true)
 {
     if (!X) return fail(nullptr, NMF_E_INVAL, "X is NULL");
     if (X->m < 1 || X->n < 1)
@@ -157,10 +228,9 @@ nmf_status check_matrix(const nmf_matrix *X)
         return fail(nullptr, NMF_E_UNSUPPORTED, "X dimensions above 2^31 are not provided");
     if (X->fmt == NMF_DENSE_ROWMAJOR) {
         if (!X->dense) return fail(nullptr, NMF_E_INVAL, "dense X has a NULL pointer");
-        const int64_t cnt = X->m * X->n;
-        for (int64_t i = 0; i < cnt; ++i)
-            if (!std::isfinite(X->dense[i]))
-                return fail(nullptr, NMF_E_INVAL, "X has a non-finite entry at %lld", (long long)i);
+        const int64_t bad = scan_dense ? first_nonfinite(X->dense, X->m * X->n) : -1;
+        if (bad >= 0)
+            return fail(nullptr, NMF_E_INVAL, "X has a non-finite entry at %lld", (long long)bad);
         return NMF_OK;
     }
     if (X->fmt == NMF_CSR) {
@@ -480,7 +550,12 @@ namespace nmf {
 namespace host {
 void set_error(const std::string &msg) { g_err = msg; }
 nmf_status check_params(const nmf_params *p) { return ::check_params(p); }
-nmf_status check_matrix(const nmf_matrix *X) { return ::check_matrix(X); }
+nmf_status check_matrix(const nmf_matrix *X) { return ::check_matrix(X, true); }
+nmf_status check_matrix_shape(const nmf_matrix *X) { return ::check_matrix(X, false); }
+int64_t copy_checked(const float *src, float *dst, int64_t cnt, bool *nonzero)
+{
+    return ::copy_checked(src, dst, cnt, nonzero);
+}
 int round_rank(int r) { return ::round_rank(r); }
 int64_t round_up(int64_t v, int64_t q) { return ::round_up(v, q); }
 void plan_product(ProdArgs &a, int kernel, int64_t rows, int64_t rows_pad, int64_t K, int64_t ld,
