@@ -49,7 +49,7 @@ XBYTES = {"f32": 4, "bf16": 2, "f16": 2}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--m", type=int, default=16384)
     ap.add_argument("--n", type=int, default=16384)
