@@ -191,11 +191,14 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
                     for (int v = 0; v < kQFast; ++v)
                         S[u][v] = (u < q && v < q) ? s_ginv[ni[u] * RP + ni[v]] : (u == v ? 1.0 : 0.0);
                 }
-                // (G^-1)_NN l = z_N by symmetric elimination and back substitution.
+                // (G^-1)_NN l = z_N by symmetric elimination and back substitution
+                // (the pivots' reciprocals kept for the latter).
+                double rpiv[kQFast];
 #pragma unroll
                 for (int pp = 0; pp < kQFast; ++pp) {
                     if (pp < q && !(S[pp][pp] > 0.0)) fail = true;
                     const double inv = 1.0 / S[pp][pp];
+                    rpiv[pp] = inv;
 #pragma unroll
                     for (int i = pp + 1; i < kQFast; ++i) {
                         const double f = S[i][pp] * inv;
@@ -209,7 +212,7 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
                     double v = lz[pp];
 #pragma unroll
                     for (int j = pp + 1; j < kQFast; ++j) v = fma(-S[pp][j], lz[j], v);
-                    lz[pp] = v / S[pp][pp];
+                    lz[pp] = v * rpiv[pp];
                 }
                 // x = z - G^-1(:,N) l on the passive set; y_N = -l.
                 double xf = zs[lane];
