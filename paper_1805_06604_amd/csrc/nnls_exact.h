@@ -101,15 +101,20 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
             s_colp[threadIdx.x] = s_ginv[threadIdx.x * RP + p];
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < RP * RP; e += kThreads) {
-            const int i = e / RP, j = e % RP;
-            double v;
-            if (i == p && j == p) v = inv;
-            else if (i == p) v = s_rowp[j] * inv;
-            else if (j == p) v = -s_colp[i] * inv;
-            else v = s_ginv[e] - s_colp[i] * s_rowp[j] * inv;
-            s_ginv[e] = v;
+        // A fixed number of entries per thread, unrolled, so that the LDS
+        // reads of a pivot step are all in flight together.
+        static_assert(RP * RP % kThreads == 0, "whole entries per thread");
+        double v[RP * RP / kThreads];
+#pragma unroll
+        for (int u = 0; u < RP * RP / kThreads; ++u) {
+            const int e = u * kThreads + threadIdx.x, i = e / RP, j = e % RP;
+            if (i == p && j == p) v[u] = inv;
+            else if (i == p) v[u] = s_rowp[j] * inv;
+            else if (j == p) v[u] = -s_colp[i] * inv;
+            else v[u] = s_ginv[e] - s_colp[i] * s_rowp[j] * inv;
         }
+#pragma unroll
+        for (int u = 0; u < RP * RP / kThreads; ++u) s_ginv[u * kThreads + threadIdx.x] = v[u];
         __syncthreads();
     }
     __syncthreads();
