@@ -105,13 +105,21 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
         // reads of a pivot step are all in flight together.
         static_assert(RP * RP % kThreads == 0, "whole entries per thread");
         double v[RP * RP / kThreads];
+        // Every operand is read and the case is a select: no branch keeps
+        // the reads of one entry from overlapping the others'. When the
+        // threads of a workgroup span whole rows, a thread's column (and so
+        // A(p,j)/a) is the same for all its entries.
+        constexpr bool kFixedCol = kThreads % RP == 0;
+        const double rjs0 = kFixedCol ? s_rowp[threadIdx.x % RP] * inv : 0.0;
 #pragma unroll
         for (int u = 0; u < RP * RP / kThreads; ++u) {
             const int e = u * kThreads + threadIdx.x, i = e / RP, j = e % RP;
-            if (i == p && j == p) v[u] = inv;
-            else if (i == p) v[u] = s_rowp[j] * inv;
-            else if (j == p) v[u] = -s_colp[i] * inv;
-            else v[u] = s_ginv[e] - s_colp[i] * s_rowp[j] * inv;
+            const double rjs = kFixedCol ? rjs0 : s_rowp[j] * inv;
+            const double ci = s_colp[i], aij = s_ginv[e];
+            double w = fma(-ci, rjs, aij);
+            w = (j == p) ? -ci * inv : w;
+            w = (i == p) ? rjs : w;
+            v[u] = (i == p && j == p) ? inv : w;
         }
 #pragma unroll
         for (int u = 0; u < RP * RP / kThreads; ++u) s_ginv[u * kThreads + threadIdx.x] = v[u];
