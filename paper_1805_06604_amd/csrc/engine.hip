@@ -36,6 +36,10 @@ struct nmf_ctx {
     double nx2 = 0.0;
     Buffers b;
     hipStream_t own = nullptr;
+    // E-ANLS: a second stream on which the Gram inversions run beside the
+    // products (fork and join events per side).
+    hipStream_t side = nullptr;
+    hipEvent_t fork[2] = {nullptr, nullptr}, join[2] = {nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool started = false;
@@ -269,9 +273,14 @@ void free_all(nmf_ctx *c)
     void *ptrs[] = {c->X, c->Xt, c->zexp_x, c->zexp_xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH,
                     c->b.A, c->b.Ct, c->b.part_g, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
                     c->b.accepted, c->b.beta_used, c->b.beta_star, c->b.stage, c->b.fsl, c->b.texp,
-                    c->b.x64, c->b.part_n, c->b.sweeps};
+                    c->b.x64, c->b.part_n, c->b.sweeps, c->b.ginv_h, c->b.ginv_w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (int i = 0; i < 2; ++i) {
+        if (c->fork[i]) (void)hipEventDestroy(c->fork[i]);
+        if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+    }
+    if (c->side) (void)hipStreamDestroy(c->side);
     if (c->own) (void)hipStreamDestroy(c->own);
 }
 
@@ -316,6 +325,10 @@ nmf_status alloc_buffers(nmf_ctx *c)
         HIP_TRY(c, dalloc(&b.part_n, (size_t)nblk));
         HIP_TRY(c, dalloc(&b.sweeps, (size_t)2 * std::max(c->p.max_iter, 1)));
         HIP_TRY(c, hipMemsetAsync(b.sweeps, 0, sizeof(int32_t) * 2 * std::max(c->p.max_iter, 1), c->own));
+    }
+    if (c->p.inner_rule == NMF_INNER_EXACT) {
+        HIP_TRY(c, dalloc(&b.ginv_h, (size_t)rp * rp + 1));
+        HIP_TRY(c, dalloc(&b.ginv_w, (size_t)rp * rp + 1));
     }
     if (c->prod_kernel == nmf::PK_MFMA_I8 || c->prod_kernel == nmf::PK_MFMA_X16) {
         // Both products slice their factor into one shared buffer (they run in
@@ -507,17 +520,37 @@ nmf_status enqueue_iteration(nmf_ctx *c, hipStream_t s, hipEvent_t *ev = nullptr
     Buffers &b = c->b;
     auto e = [&](int i) { return ev ? ev[i] : nullptr; };
     // a1: C^T = X^T W_y ; a2-a4: H sweeps + epilogue ; a5: A = X H_w^T ;
-    // a6-a8: W sweeps + epilogue + decision.
+    // a6-a8: W sweeps + epilogue + decision. Exact solves: the inverse of
+    // each Gram matrix is taken on the side stream while the product that
+    // precedes its solve runs (fork after the Gram is final, join before the
+    // solve).
+    auto fork = [&](int side) -> nmf_status {
+        HIP_TRY(c, hipEventRecord(c->fork[side], s));
+        HIP_TRY(c, hipStreamWaitEvent(c->side, c->fork[side], 0));
+        HIP_TRY(c, nmf::launch_invert(rp, side == 1, c->r, b, c->side));
+        HIP_TRY(c, hipEventRecord(c->join[side], c->side));
+        return NMF_OK;
+    };
+    if (exact) {
+        const nmf_status fs = fork(0);
+        if (fs != NMF_OK) return fs;
+    }
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SLICE_W], s));
     HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pc, s, e(NMF_PHASE_PROD_CT)));
+    if (exact) HIP_TRY(c, hipStreamWaitEvent(s, c->join[0], 0));
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SWEEP_H], s));
     if (adaptive)
         HIP_TRY(c, nmf::launch_sweep_h_adaptive(rp, c->n, c->r, c->cap_h, c->p.inner_delta, b, s,
                                                 e(NMF_PHASE_FINISH_H)));
     else
         HIP_TRY(c, nmf::launch_sweep_h(rp, c->n, c->r, c->p.inner_k, exact, b, s, e(NMF_PHASE_FINISH_H)));
+    if (exact) {
+        const nmf_status fs = fork(1);
+        if (fs != NMF_OK) return fs;
+    }
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SLICE_H], s));
     HIP_TRY(c, nmf::launch_product(rp, xd, pk, c->pa, s, e(NMF_PHASE_PROD_A)));
+    if (exact) HIP_TRY(c, hipStreamWaitEvent(s, c->join[1], 0));
     if (ev) HIP_TRY(c, hipEventRecord(ev[NMF_PHASE_SWEEP_W], s));
     if (adaptive)
         HIP_TRY(c, nmf::launch_sweep_w_adaptive(rp, c->m, c->r, c->cap_w, c->p.inner_delta, b, s,
@@ -633,6 +666,13 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
     }
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking);
+    if (e == hipSuccess && p->inner_rule == NMF_INNER_EXACT) {
+        e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+            e = hipEventCreateWithFlags(&c->fork[i], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming);
+        }
+    }
     if (e != hipSuccess) {
         fail(nullptr, NMF_E_DEVICE, "no usable HIP device: %s", hipGetErrorString(e));
         free_all(c);

@@ -102,6 +102,12 @@ hipError_t launch_sweep_w_adaptive(int rp, int64_t m, int r, int cap, double del
     return hipGetLastError();
 }
 
+hipError_t launch_invert(int rp, bool w_side, int r, const Buffers &b, hipStream_t s)
+{
+    NMF_RP_CALL(rp, invert, w_side, r, b, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_group_exact(int rp, bool w_side, const Group &g, int blocks, hipStream_t s)
 {
     NMF_RP_CALL(rp, exact_group, w_side, g, blocks, s);

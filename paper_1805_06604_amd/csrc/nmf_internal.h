@@ -174,6 +174,9 @@ struct Buffers {
     // sweeps (max(m, n) x RP), the per-workgroup squared changes of a sweep,
     // and the sweeps run per iteration (H, W).
     double *x64 = nullptr;
+    // E-ANLS: the inverses of G_W (H solve) and G_H (W solve), RP x RP and a
+    // 1 / 0 flag each, computed once per side beside the preceding product.
+    double *ginv_h = nullptr, *ginv_w = nullptr;
     double *part_n = nullptr;
     int32_t *sweeps = nullptr;
 };
@@ -270,6 +273,9 @@ hipError_t launch_group(int rp, const Group &gs, int sblocks, const Group &gp, i
                         hipStream_t s);
 }
 hipError_t launch_group_exact(int rp, bool w_side, const Group &g, int blocks, hipStream_t s);
+// E-ANLS: the inverse of the Gram matrix the H (w_side false) or W solve uses,
+// into b.ginv_h / b.ginv_w (one workgroup).
+hipError_t launch_invert(int rp, bool w_side, int r, const Buffers &b, hipStream_t s);
 hipError_t launch_group_sweep(int rp, bool w_side, const Group &gh, int hblocks, const Group &gf,
                               int fblocks, hipStream_t s);
 

@@ -49,50 +49,28 @@ struct ExactShape {
     static constexpr int NSEG = 64 / SEG;                             // problems per wave
 };
 
-template <int RP, int MODE>
-__device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
+// G^-1 of the r x r Gram matrix in s_g (RP x RP, read after a barrier the
+// caller has passed) into s_ginv, *s_ok = 0 where a pivot fails; every thread
+// of the workgroup takes part and the result is visible to all on return.
+template <int RP>
+__device__ __forceinline__ void invert_gram(int r, const double *s_g, double *s_ginv, double *s_rowp,
+                                            double *s_colp, int *s_ok)
 {
-    constexpr int SEG = ExactShape<RP>::SEG, NSEG = ExactShape<RP>::NSEG;
-    constexpr int PASSES = kExactRows / (kWaves * NSEG);
-    static_assert(PASSES * kWaves * NSEG == kExactRows, "rows per workgroup");
-    __shared__ double s_g[RP * RP];
-    __shared__ double s_col[kWaves][64];
-    __shared__ double s_b[kWaves][64];
-    __shared__ double s_x[kWaves][64];
-    __shared__ double s_d[kWaves][64];
-    __shared__ double s_ginv[RP * RP];
-    __shared__ double s_z[kWaves][64];
-    __shared__ double s_rowp[RP], s_colp[RP];
-    __shared__ int s_ginv_ok;
-
-    DevState *st = a.st;
-    if (st->done) return;
-    int src, dst;
-    const double *G = a.gram;
-    if constexpr (MODE == SWEEP_H) {
-        src = st->h_y; dst = st->h_n;
-        G += (int64_t)st->w_y * a.gram_slot_stride;
-    } else {
-        src = st->w_y; dst = st->w_n;
-    }
-    for (int e = threadIdx.x; e < RP * RP; e += kThreads) s_g[e] = G[e];
-    __syncthreads();
-
     // G^-1 on the coordinates with a positive diagonal (zero elsewhere), by
     // in-place Gauss-Jordan: pivot p maps a = A(p,p) to 1/a, row p to A(p,j)/a,
     // column p to -A(i,p)/a and the rest to A(i,j) - A(i,p) A(p,j)/a.
-    auto posc = [&](int i) { return i < a.r && s_g[i * RP + i] > 0.0; };
+    auto posc = [&](int i) { return i < r && s_g[i * RP + i] > 0.0; };
     for (int e = threadIdx.x; e < RP * RP; e += kThreads) {
         const int i = e / RP, j = e % RP;
         s_ginv[e] = (posc(i) && posc(j)) ? s_g[e] : 0.0;
     }
-    if (threadIdx.x == 0) s_ginv_ok = 1;
+    if (threadIdx.x == 0) *s_ok = 1;
     __syncthreads();
     for (int p = 0; p < RP; ++p) {
         if (!posc(p)) continue;
         const double piv = s_ginv[p * RP + p];
         if (!(piv > 1e-10 * s_g[p * RP + p])) {
-            if (threadIdx.x == 0) s_ginv_ok = 0;
+            if (threadIdx.x == 0) *s_ok = 0;
             break;
         }
         const double inv = 1.0 / piv;
@@ -126,6 +104,45 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
         __syncthreads();
     }
     __syncthreads();
+}
+
+template <int RP, int MODE>
+__device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
+{
+    constexpr int SEG = ExactShape<RP>::SEG, NSEG = ExactShape<RP>::NSEG;
+    constexpr int PASSES = kExactRows / (kWaves * NSEG);
+    static_assert(PASSES * kWaves * NSEG == kExactRows, "rows per workgroup");
+    __shared__ double s_g[RP * RP];
+    __shared__ double s_col[kWaves][64];
+    __shared__ double s_b[kWaves][64];
+    __shared__ double s_x[kWaves][64];
+    __shared__ double s_d[kWaves][64];
+    __shared__ double s_ginv[RP * RP];
+    __shared__ double s_z[kWaves][64];
+    __shared__ double s_rowp[RP], s_colp[RP];
+    __shared__ int s_ginv_ok;
+
+    DevState *st = a.st;
+    if (st->done) return;
+    int src, dst;
+    const double *G = a.gram;
+    if constexpr (MODE == SWEEP_H) {
+        src = st->h_y; dst = st->h_n;
+        G += (int64_t)st->w_y * a.gram_slot_stride;
+    } else {
+        src = st->w_y; dst = st->w_n;
+    }
+    for (int e = threadIdx.x; e < RP * RP; e += kThreads) s_g[e] = G[e];
+    __syncthreads();
+
+    if (a.ginv) {
+        // Taken beforehand, once for all workgroups (invert_kernel).
+        for (int e = threadIdx.x; e < RP * RP; e += kThreads) s_ginv[e] = a.ginv[e];
+        if (threadIdx.x == 0) s_ginv_ok = a.ginv[RP * RP] != 0.0;
+        __syncthreads();
+    } else {
+        invert_gram<RP>(a.r, s_g, s_ginv, s_rowp, s_colp, &s_ginv_ok);
+    }
     const bool ginv_ok = s_ginv_ok != 0;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -334,6 +351,27 @@ template <int RP, int MODE>
 __global__ __launch_bounds__(kThreads, 2) void exact_kernel(HalsArgs a)
 {
     exact_body<RP, MODE>(a, blockIdx.x);
+}
+
+// The inverse for all workgroups of one exact solve, taken once (one
+// workgroup) while the product that precedes the solve runs: RP x RP entries
+// of G^-1, then 1.0 where every pivot held, 0.0 where one failed.
+template <int RP, int MODE>
+__global__ __launch_bounds__(kThreads) void invert_kernel(HalsArgs a)
+{
+    __shared__ double s_g[RP * RP];
+    __shared__ double s_ginv[RP * RP];
+    __shared__ double s_rowp[RP], s_colp[RP];
+    __shared__ int s_ok;
+    const DevState *st = a.st;
+    if (st->done) return;
+    const double *G = a.gram;
+    if constexpr (MODE == SWEEP_H) G += (int64_t)st->w_y * a.gram_slot_stride;
+    for (int e = threadIdx.x; e < RP * RP; e += kThreads) s_g[e] = G[e];
+    __syncthreads();
+    invert_gram<RP>(a.r, s_g, s_ginv, s_rowp, s_colp, &s_ok);
+    for (int e = threadIdx.x; e < RP * RP; e += kThreads) a.ginv[e] = s_ginv[e];
+    if (threadIdx.x == 0) a.ginv[RP * RP] = s_ok ? 1.0 : 0.0;
 }
 
 // Grouped form: one launch over the problems of a group that solve their

@@ -176,6 +176,9 @@ struct HalsArgs {
     int step;
     double *x64;
     double *part_n;
+    // Exact solve: the inverse of the Gram matrix (RP x RP, then a 1 / 0 flag)
+    // computed beforehand, or null for an inversion in every workgroup.
+    double *ginv;
 };
 
 // SETUP_H / SETUP_W: Gram (and for W, <W0, A>) of slot 0.
@@ -699,6 +702,8 @@ template <int RP, int MODE>
 __global__ __launch_bounds__(kThreads, 2) void exact_kernel(HalsArgs a);
 template <int RP, int MODE>
 __global__ __launch_bounds__(kThreads, 2) void exact_group_kernel(Group g);
+template <int RP, int MODE>
+__global__ __launch_bounds__(kThreads) void invert_kernel(HalsArgs a);
 inline int exact_blocks(int64_t rows) { return (int)((rows + kExactRows - 1) / kExactRows); }
 
 // Argument records of one half-iteration (or set-up step) of one problem.
@@ -725,6 +730,7 @@ inline HalsArgs hals_args(int rp, int64_t rows, int r, int K, const Buffers &b, 
     }
     h.part = b.part_g;
     h.st = b.st;
+    h.ginv = w_side ? b.ginv_w : b.ginv_h;
     return h;
 }
 
@@ -829,6 +835,12 @@ struct Launch {
                                  hipStream_t s, hipEvent_t mid)
     {
         adaptive<SWEEP_W>(m, r, cap, delta, b, true, b.counters + CNT_W, s, mid);
+    }
+    static void invert(bool w_side, int r, const Buffers &b, hipStream_t s)
+    {
+        const HalsArgs h = hals_args(RP, 0, r, 0, b, w_side);
+        if (w_side) invert_kernel<RP, SWEEP_W><<<1, kThreads, 0, s>>>(h);
+        else invert_kernel<RP, SWEEP_H><<<1, kThreads, 0, s>>>(h);
     }
     static void sweep_h(int64_t n, int r, int K, bool exact, const Buffers &b, hipStream_t s,
                         hipEvent_t mid)

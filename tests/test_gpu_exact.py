@@ -163,3 +163,28 @@ def test_device_pointer_interface():
     np.testing.assert_array_equal(a.trace, b.trace)
     np.testing.assert_array_equal(a.W, W.cpu().numpy())
     np.testing.assert_array_equal(a.H, H.cpu().numpy())
+
+
+@pytest.mark.parametrize("m,n,r", [(180, 150, 7), (200, 170, 20), (150, 260, 40), (240, 210, 64)])
+def test_inverse_beside_product_matches_inverse_per_workgroup(m, n, r):
+    """A single context takes G^-1 once per side on a second stream, beside the
+    product before the solve; the batch engine's grouped solves invert G in
+    every workgroup with the same code. Both therefore solve with the same
+    inverse, and the runs agree to the products' rounding."""
+    p = S.planted(11, m=m, n=n, r=r)
+    print(f"case inverse placement m={m} n={n} r={r}", flush=True)
+    kw = dict(hp=1, inner_rule=P.Inner.EXACT, **ALG)
+    with P.Solver(p.X, p.r, max_iter=30, prod=P.Prod.MFMA_EXACT, **kw) as s:
+        single = s.solve(p.W0, p.H0)
+    res = None
+    with P.Batch(1 << 28, max_active=4, check_every=5) as B:
+        t = B.submit(p.X, p.r, p.W0, p.H0, max_iter=30, **kw)
+        for _ in range(50):
+            B.step(30)
+            res = B.result(t)
+            if res is not None:
+                break
+    assert res is not None and res.n_iter == single.n_iter
+    np.testing.assert_allclose(res.trace, single.trace, rtol=1e-6)
+    for a, b in ((res.W, single.W), (res.H, single.H)):
+        assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b)
