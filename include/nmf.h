@@ -176,7 +176,11 @@ nmf_status nmf_solve(nmf_ctx *ctx, const float *W0, const float *H0, float *W,
  *
  * nmf_iterate: enqueues `iters` outer iterations on `stream` and returns
  * without waiting. Iterations past max_iter, or after the tol stop, do
- * nothing. Errors: NMF_E_STATE before nmf_start, NMF_E_INVAL for iters < 0.
+ * nothing. With NMF_INNER_EXACT, part of each iteration (the inverse of each
+ * Gram matrix) runs on a stream of the context, forked from `stream` and
+ * joined back within the iteration, so every iteration still starts after
+ * the work enqueued on `stream` before it and ends before the work enqueued
+ * after it. Errors: NMF_E_STATE before nmf_start, NMF_E_INVAL for iters < 0.
  *
  * nmf_read: waits for `stream`, then copies the last accepted W (m*r) and H
  * (r*n) into host (on_device = 0) or device (on_device = 1) arrays, and the
