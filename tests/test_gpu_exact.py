@@ -188,3 +188,27 @@ def test_inverse_beside_product_matches_inverse_per_workgroup(m, n, r):
     np.testing.assert_allclose(res.trace, single.trace, rtol=1e-6)
     for a, b in ((res.W, single.W), (res.H, single.H)):
         assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("rule", ["FIXED", "EXACT"])
+def test_profiled_iterations_match_graph_iterations(rule):
+    """Iterations launched one kernel at a time (nmf_profile; with exact
+    solves, the inversions forked to the context's second stream and joined
+    back outside any graph) interleaved with graph iterations reproduce a
+    plain solve bitwise."""
+    p = S.planted(12, m=300, n=260, r=24)
+    kw = dict(hp=1, inner_rule=P.Inner[rule], inner_k=10, **ALG)
+    print(f"case profiled/graph interleave rule={rule}", flush=True)
+    with P.Solver(p.X, p.r, max_iter=20, **kw) as s:
+        plain = s.solve(p.W0, p.H0)
+    with P.Solver(p.X, p.r, max_iter=20, **kw) as s:
+        s.start(p.W0, p.H0)
+        s.iterate(5)
+        ms = s.profile(5)
+        s.iterate(10)
+        mixed = s.read()
+    assert all(v >= 0.0 for v in ms.values())
+    assert mixed.n_iter == plain.n_iter == 20
+    np.testing.assert_array_equal(mixed.trace, plain.trace)
+    np.testing.assert_array_equal(mixed.W, plain.W)
+    np.testing.assert_array_equal(mixed.H, plain.H)
