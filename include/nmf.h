@@ -45,8 +45,10 @@ typedef enum {
 
 typedef enum { NMF_DENSE_ROWMAJOR = 0, NMF_CSR = 1 } nmf_format;
 
-/* Storage type of X on the device. Products accumulate in FP32 and the
- * objective combination runs in FP64 whatever this is. */
+/* Storage type of X on the device. The values are rounded to this type once;
+ * how the products then accumulate is set by nmf_prod below (exact integer
+ * sums, FP64, or FP32 within a K-chunk), and the objective combination runs
+ * in FP64 whatever this is. */
 typedef enum { NMF_X_F32 = 0, NMF_X_BF16 = 1, NMF_X_F16 = 2 } nmf_xdtype;
 
 /* How each block subproblem (the NNLS in H with W fixed, then in W with H
@@ -191,6 +193,18 @@ nmf_status nmf_iterate(nmf_ctx *ctx, int32_t iters, void *stream);
 nmf_status nmf_read(nmf_ctx *ctx, float *W, float *H, int32_t on_device,
                     double *trace, int32_t trace_cap, int32_t *n_iter,
                     uint8_t *accepted, double *beta, void *stream);
+
+/* Test hook of the restart branch of Algorithm 2 (reading: a non-finite
+ * e(k) is a restart and does not replace the previous error; a non-finite
+ * e(0) is NMF_E_NUMERIC). From the next nmf_start (or nmf_solve) on, the
+ * squared error e(k)^2 of iteration k is multiplied by scale[k] for
+ * k < count before it is tested (k = 0: e(0)); a NaN or infinite factor
+ * forces the non-finite branch, a large one a forced increase. The host
+ * array is copied (count doubles); count = 0 removes the hook. The
+ * iterates themselves are not touched. Synchronizes the device.
+ * Errors: NMF_E_INVAL (count < 0, or scale NULL with count > 0),
+ * NMF_E_DEVICE. */
+nmf_status nmf_set_error_scale(nmf_ctx *ctx, const double *scale, int32_t count);
 
 /* Kernels of one outer iteration, in launch order (the phases timed by
  * nmf_profile). The slicing phases run only with the exact-integer products

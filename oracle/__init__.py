@@ -20,6 +20,7 @@ ERR_REMARK1 = 4
 ROUND_F32 = 8
 EXACT_NNLS = 16
 ADAPTIVE_INNER = 32
+ROUND_F32_RZ = 64
 
 _lib = None
 
@@ -36,7 +37,8 @@ class _Params(C.Structure):
                 ("inner_k", C.c_int), ("max_iter", C.c_int),
                 ("tol", C.c_double), ("flags", C.c_int),
                 ("replay", C.c_void_p), ("inner_alpha", C.c_double),
-                ("inner_delta", C.c_double), ("sweeps_replay", C.c_void_p)]
+                ("inner_delta", C.c_double), ("sweeps_replay", C.c_void_p),
+                ("e2_scale", C.c_void_p), ("e2_scale_n", C.c_int)]
 
 
 def lib():
@@ -86,12 +88,14 @@ class _Held:
 
 def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
           eta=1.5, inner_k=10, max_iter=100, tol=0.0, flags=0, replay=None,
-          inner_alpha=0.5, inner_delta=0.1, sweeps_replay=None):
+          inner_alpha=0.5, inner_delta=0.1, sweeps_replay=None, e2_scale=None):
     """Run Alg. 2 with Alg. 3 and return a dict with W, H (last accepted),
     trace (rho(0..n_iter)), accepted, beta, margin, beta_star (section 4,
     per iteration), sweeps (HALS sweeps on H and on W per iteration),
     sweep_margin (closest call of each adaptive stop decision) and n_iter.
-    sweeps_replay forces the adaptive sweep counts ((max_iter, 2) array)."""
+    sweeps_replay forces the adaptive sweep counts ((max_iter, 2) array).
+    e2_scale (test hook): factors applied to e(k)^2 for k = 0, 1, ... before
+    the test of Algorithm 2 (NaN or inf drive its non-finite branch)."""
     h = _Held(X)
     W0 = np.ascontiguousarray(W0, dtype=np.float64).reshape(h.m, r)
     H0 = np.ascontiguousarray(H0, dtype=np.float64).reshape(r, h.n)
@@ -114,9 +118,13 @@ def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
         rp = np.ascontiguousarray(replay, dtype=np.uint8)
         if rp.size < max_iter:
             raise ValueError("replay needs max_iter decisions")
+    es = None
+    if e2_scale is not None:
+        es = np.ascontiguousarray(e2_scale, dtype=np.float64).ravel()
     prm = _Params(hp, beta0, gamma, gamma_bar, eta, inner_k, max_iter, tol,
                   flags, None if rp is None else _ptr(rp).value, inner_alpha, inner_delta,
-                  None if sr is None else _ptr(sr).value)
+                  None if sr is None else _ptr(sr).value,
+                  None if es is None else _ptr(es).value, 0 if es is None else es.size)
     nit = C.c_int(0)
     st = lib().oracle_eahals(C.byref(h.s), r, _ptr(W0), _ptr(H0), C.byref(prm),
                              _ptr(W), _ptr(H), _ptr(trace), _ptr(acc),

@@ -312,6 +312,24 @@ static double remark1_err2(int64_t m, int r, double nx2, const double *W,
     return nx2 - 2.0 * s1 + s2;
 }
 
+/* e from e^2 (R9): the Remark-1 combination can round slightly below zero,
+ * which is clamped to 0; a non-finite e^2 stays non-finite (NaN stays NaN,
+ * an infinite e^2 gives +inf), so that the test of Algorithm 2 sees it and
+ * restarts instead of accepting an error of 0. */
+static double err_of_sq(double e2)
+{
+    if (!isfinite(e2)) return fabs(e2);
+    return sqrt(e2 > 0.0 ? e2 : 0.0);
+}
+
+/* Test hook: e(k)^2 times the caller's factor for iteration k (k = 0 is the
+ * initial error); no factor applies past e2_scale_n. */
+static double scaled_err2(const oracle_params *p, int k, double e2)
+{
+    if (p->e2_scale && k < p->e2_scale_n) e2 *= p->e2_scale[k];
+    return e2;
+}
+
 /* Section 4: the beta that minimizes ||X - (W_n + beta (W_n - W)) H_w||_F^2
  * over beta. With dW = W_n - W, A = X H_w^T and B = H_w H_w^T, the objective
  * is a quadratic in beta whose minimizer is
@@ -406,8 +424,15 @@ static int valid_matrix(const oracle_matrix *X)
  * storage of the iterates in single precision, nothing else). */
 static void round_f32(int64_t len, double *v, int flags)
 {
-    if (!(flags & ORACLE_ROUND_F32)) return;
-    for (int64_t i = 0; i < len; ++i) v[i] = (double)(float)v[i];
+    if (flags & ORACLE_ROUND_F32) {
+        for (int64_t i = 0; i < len; ++i) v[i] = (double)(float)v[i];
+    } else if (flags & ORACLE_ROUND_F32_RZ) {
+        for (int64_t i = 0; i < len; ++i) {
+            float f = (float)v[i];
+            if (fabs((double)f) > fabs(v[i])) f = nextafterf(f, 0.0f);
+            v[i] = (double)f;
+        }
+    }
 }
 
 /* Extrapolation: Y = N + beta (N - P), optionally projected onto Y >= 0. */
@@ -508,14 +533,15 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
     memcpy(H, H0, sizeof(double) * rn);
     memcpy(Wy, W, sizeof(double) * mr);
     memcpy(Hy, H, sizeof(double) * rn);
-    double e0;
+    double e0sq;
     if (p->flags & ORACLE_ERR_REMARK1) {
         x_ht(X, r, H, A);
         gram_rows(n, r, H, B);
-        e0 = sqrt(fmax(0.0, remark1_err2(m, r, nx2, W, A, B)));
+        e0sq = remark1_err2(m, r, nx2, W, A, B);
     } else {
-        e0 = sqrt(explicit_err2(X, r, W, H));
+        e0sq = explicit_err2(X, r, W, H);
     }
+    const double e0 = err_of_sq(scaled_err2(p, 0, e0sq));
     if (!isfinite(e0)) { status = ORACLE_ENUMERIC; goto done; }
     trace[0] = e0 / nx;
 
@@ -573,10 +599,10 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         round_f32(mr, Wyn, p->flags);
 
         /* e(k) = ||X - W_n H_w||_F. */
-        double e2 = (p->flags & ORACLE_ERR_REMARK1)
-                        ? fmax(0.0, remark1_err2(m, r, nx2, Wn, A, B))
-                        : explicit_err2(X, r, Wn, Hw);
-        const double e = sqrt(e2);
+        const double e2 = (p->flags & ORACLE_ERR_REMARK1)
+                              ? remark1_err2(m, r, nx2, Wn, A, B)
+                              : explicit_err2(X, r, Wn, Hw);
+        const double e = err_of_sq(scaled_err2(p, k, e2));
         trace[k] = e / nx;
 
         const double e_cmp = (p->flags & ORACLE_CMP_LAST_ACCEPTED) ? e_acc : e_prev;
@@ -702,5 +728,5 @@ double oracle_rel_error_remark1(const oracle_matrix *X, int r, const double *W,
     const double nx2 = frob2(X);
     const double e2 = remark1_err2(m, r, nx2, W, A, B);
     free(A); free(B);
-    return sqrt(fmax(0.0, e2) / nx2);
+    return err_of_sq(e2) / sqrt(nx2);
 }

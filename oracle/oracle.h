@@ -31,7 +31,9 @@
  *       not; ORACLE_CMP_LAST_ACCEPTED compares with the last accepted e.
  *   R8  Equality accepts (the test of Alg. 2 is a strict ">").
  *   R9  A non-finite e(k) is a restart and does not replace the previous e;
- *       a non-finite e(0) is an error (ORACLE_ENUMERIC).
+ *       a non-finite e(0) is an error (ORACLE_ENUMERIC). e is sqrt(max(0,
+ *       e^2)) only for a finite e^2 (Remark 1 can round below zero); a NaN
+ *       e^2 gives a NaN e and an infinite one +inf, never 0.
  *   R10 A HALS coordinate whose denominator ||W(:,k)||^2 (or ||H(k,:)||^2)
  *       is zero does not enter the objective: it is only projected onto
  *       [0, inf) (kept when already >= 0; the warm start may be negative).
@@ -74,6 +76,9 @@ extern "C" {
 #define ORACLE_ROUND_F32             8  /* round the stored iterates W_n, H_n, W_y, H_y
                                            to FP32 after each update (conditioning
                                            probe; all arithmetic stays FP64)       */
+#define ORACLE_ROUND_F32_RZ         64  /* the same probe with rounding toward
+                                           zero (a second, independent
+                                           perturbation of the same size)     */
 #define ORACLE_ADAPTIVE_INNER       32  /* adaptive A-HALS inner loop (R18) instead of
                                            inner_k sweeps                          */
 #define ORACLE_EXACT_NNLS           16  /* E-ANLS: solve each NNLS block exactly
@@ -101,6 +106,12 @@ typedef struct {
     double inner_delta;       /*   weight alpha and stopping ratio delta    */
     const int *sweeps_replay; /* NULL, or 2 max_iter forced sweep counts
                                  (H, W per iteration) for the adaptive loop */
+    const double *e2_scale;   /* test hook, NULL or e2_scale_n factors:
+                                 e(k)^2 is multiplied by e2_scale[k] before
+                                 the test of Alg. 2 (k = 0: e(0)); a NaN or
+                                 infinite factor drives the non-finite
+                                 branch of R9                              */
+    int e2_scale_n;
 } oracle_params;
 
 /* Full solve (Alg. 2 with Alg. 3). Outputs, all caller-allocated:

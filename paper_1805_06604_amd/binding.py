@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libnmf.so")
 
 EXPORTS = ("nmf_params_default", "nmf_create", "nmf_solve", "nmf_start",
            "nmf_iterate", "nmf_read", "nmf_profile", "nmf_destroy",
-           "nmf_last_error", "nmf_read_beta_star", "nmf_read_sweeps", "nmf_batch_create", "nmf_batch_submit", "nmf_batch_step",
+           "nmf_last_error", "nmf_read_beta_star", "nmf_read_sweeps", "nmf_set_error_scale",
+           "nmf_batch_create", "nmf_batch_submit", "nmf_batch_step",
            "nmf_batch_result", "nmf_batch_destroy")
 
 
@@ -131,6 +132,8 @@ def lib():
         L.nmf_read_beta_star.restype = i32
         L.nmf_read_sweeps.argtypes = [p, p, i32, p]
         L.nmf_read_sweeps.restype = i32
+        L.nmf_set_error_scale.argtypes = [p, p, i32]
+        L.nmf_set_error_scale.restype = i32
         L.nmf_batch_create.argtypes = [p, p]
         L.nmf_batch_create.restype = i32
         L.nmf_batch_submit.argtypes = [p, p, p, p, p, p]
@@ -158,6 +161,33 @@ def make_params(r, **kw) -> Params:
 
 def _ptr(a):
     return C.c_void_p(a.ctypes.data)
+
+
+def _current_device():
+    """Index of the current HIP device as torch sees it (the device a new
+    context binds to), or None without a usable torch."""
+    try:
+        import torch
+        return torch.cuda.current_device() if torch.cuda.is_available() else None
+    except ImportError:
+        return None
+
+
+def _check_device_tensor(t, shape, name, device):
+    """A torch tensor handed to the library as a raw device pointer must be a
+    contiguous float32 tensor of exactly `shape` on the context's device;
+    anything else would make the kernels read or write past it."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor like the others")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not t.is_cuda or (device is not None and t.device.index != device):
+        raise ValueError(f"{name} must live on cuda:{device}, got {t.device}")
 
 
 def _stream(stream):
@@ -205,6 +235,7 @@ class Solver:
             mat.fmt, (mat.m, mat.n) = Format.DENSE, Xd.shape
             mat.dense = Xd.ctypes.data
         self.m, self.n, self.r = int(mat.m), int(mat.n), int(r)
+        self.device = _current_device()
         st = lib().nmf_create(C.byref(mat), C.byref(self.params), C.byref(self._ctx))
         if st != Status.OK:
             raise NMFError(st, lib().nmf_last_error(None).decode())
@@ -254,10 +285,8 @@ class Solver:
     def start(self, W0, H0, stream=None):
         """nmf_start from numpy (host) or torch CUDA tensors (device)."""
         if hasattr(W0, "data_ptr"):
-            if tuple(W0.shape) != (self.m, self.r) or tuple(H0.shape) != (self.r, self.n):
-                raise ValueError("W0 must be (m, r) and H0 (r, n)")
-            if not (W0.is_contiguous() and H0.is_contiguous()):
-                raise ValueError("device W0 and H0 must be contiguous float32")
+            _check_device_tensor(W0, (self.m, self.r), "W0", self.device)
+            _check_device_tensor(H0, (self.r, self.n), "H0", self.device)
             self._check(lib().nmf_start(self._ctx, C.c_void_p(W0.data_ptr()),
                                         C.c_void_p(H0.data_ptr()), 1, _stream(stream)))
         else:
@@ -266,6 +295,15 @@ class Solver:
             if W0.shape != (self.m, self.r) or H0.shape != (self.r, self.n):
                 raise ValueError("W0 must be (m, r) and H0 (r, n)")
             self._check(lib().nmf_start(self._ctx, _ptr(W0), _ptr(H0), 0, _stream(stream)))
+
+    def set_error_scale(self, scale=None):
+        """nmf_set_error_scale (test hook): factors applied to e(k)^2 for
+        k = 0, 1, ... from the next start on; None removes them."""
+        if scale is None:
+            self._check(lib().nmf_set_error_scale(self._ctx, None, 0))
+            return
+        sc = np.ascontiguousarray(scale, dtype=np.float64).ravel()
+        self._check(lib().nmf_set_error_scale(self._ctx, _ptr(sc), sc.size))
 
     def iterate(self, iters, stream=None):
         self._check(lib().nmf_iterate(self._ctx, int(iters), _stream(stream)))
@@ -303,6 +341,8 @@ class Solver:
         beta = np.zeros(max(cap - 1, 1))
         nit = C.c_int32()
         if W is not None and hasattr(W, "data_ptr"):
+            _check_device_tensor(W, (self.m, self.r), "W", self.device)
+            _check_device_tensor(H, (self.r, self.n), "H", self.device)
             self._check(lib().nmf_read(self._ctx, C.c_void_p(W.data_ptr()),
                                        C.c_void_p(H.data_ptr()), 1, _ptr(trace), cap,
                                        C.byref(nit), _ptr(acc), _ptr(beta), _stream(stream)))

@@ -46,6 +46,8 @@ struct nmf_ctx {
     int32_t launched = 0;
     int cap_h = 0, cap_w = 0;    // adaptive inner loop: sweep caps of the two sides
     DevState hs{};       // host copy of the device state
+    double *e2_scale = nullptr;  // test hook of the restart branch (device)
+    int32_t e2_scale_n = 0;
     std::string err;
 };
 
@@ -273,7 +275,8 @@ void free_all(nmf_ctx *c)
     void *ptrs[] = {c->X, c->Xt, c->zexp_x, c->zexp_xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH,
                     c->b.A, c->b.Ct, c->b.part_g, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
                     c->b.accepted, c->b.beta_used, c->b.beta_star, c->b.stage, c->b.fsl, c->b.texp,
-                    c->b.x64, c->b.part_n, c->b.sweeps, c->b.ginv_h, c->b.ginv_w};
+                    c->b.x64, c->b.part_n, c->b.sweeps, c->b.ginv_h, c->b.ginv_w,
+                    c->e2_scale};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int i = 0; i < 2; ++i) {
@@ -765,6 +768,8 @@ nmf_status nmf_start(nmf_ctx *c, const float *W0, const float *H0, int32_t on_de
     h.gamma = c->p.gamma;
     h.gamma_bar = c->p.gamma_bar;
     h.eta = c->p.eta;
+    h.e2_scale = c->e2_scale;
+    h.e2_scale_n = c->e2_scale_n;
     const int rp = c->rp;
     Buffers &b = c->b;
     HIP_TRY(c, hipMemcpyAsync(b.st, &h, sizeof(h), hipMemcpyHostToDevice, s));
@@ -782,6 +787,23 @@ nmf_status nmf_start(nmf_ctx *c, const float *W0, const float *H0, int32_t on_de
     if (!std::isfinite(h.e0)) return fail(c, NMF_E_NUMERIC, "the initial error e(0) is not finite");
     c->started = true;
     c->launched = 0;
+    return NMF_OK;
+}
+
+nmf_status nmf_set_error_scale(nmf_ctx *c, const double *scale, int32_t count)
+{
+    if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");
+    if (count < 0 || (count > 0 && !scale))
+        return fail(c, NMF_E_INVAL, "need count >= 0 and a scale array when count > 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());     // no running iteration reads the old array
+    if (c->e2_scale) HIP_TRY(c, hipFree(c->e2_scale));
+    c->e2_scale = nullptr;
+    c->e2_scale_n = 0;
+    if (count == 0) return NMF_OK;
+    HIP_TRY(c, hipMalloc(reinterpret_cast<void **>(&c->e2_scale), sizeof(double) * count));
+    HIP_TRY(c, hipMemcpy(c->e2_scale, scale, sizeof(double) * count, hipMemcpyHostToDevice));
+    c->e2_scale_n = count;
     return NMF_OK;
 }
 

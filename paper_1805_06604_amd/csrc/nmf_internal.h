@@ -60,7 +60,22 @@ struct DevState {
     // stop flag and sweeps run so far.
     double in_eps0;
     int32_t in_stop, in_count;
+    // Test hook of the restart branch: e(k)^2 is multiplied by e2_scale[k]
+    // (device array) for k < e2_scale_n before the test of Algorithm 2; k = 0
+    // is e(0). Null and 0 when unused.
+    const double *e2_scale;
+    int32_t e2_scale_n, pad1;
 };
+
+// e from e^2: the combination of Remark 1 can round slightly below zero,
+// which is clamped to 0; a non-finite e^2 stays non-finite (NaN stays NaN,
+// an infinite one gives +inf), so that Algorithm 2 restarts on it instead of
+// accepting an error of 0.
+__device__ inline double err_of_sq(double e2)
+{
+    if (!isfinite(e2)) return fabs(e2);
+    return sqrt(e2 > 0.0 ? e2 : 0.0);
+}
 
 // Gram buffers (FP64) hold RP*RP entries, then RP inverse diagonal entries
 // (0 where the coordinate is skipped: beyond r, or a zero diagonal), then the

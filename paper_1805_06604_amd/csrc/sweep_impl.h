@@ -117,9 +117,10 @@ __device__ inline void reset_counter(uint32_t *counter)
 __device__ inline void decide(DevState *st, double s1, double s2, double *trace,
                               uint8_t *accepted, double *beta_used)
 {
-    const double e2 = st->nx2 - 2.0 * s1 + s2;               // Remark 1
-    const double e = sqrt(e2 > 0.0 ? e2 : 0.0);
     const int k = st->k + 1;
+    double e2 = st->nx2 - 2.0 * s1 + s2;                     // Remark 1
+    if (k < st->e2_scale_n) e2 *= st->e2_scale[k];
+    const double e = err_of_sq(e2);
     trace[k] = e / sqrt(st->nx2);
     const double e_cmp = (st->flags & 2) ? st->e_acc : st->e_prev;
     const bool fin = isfinite(e);
@@ -615,8 +616,9 @@ __device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
                 decide(st, s1, s2, a.trace, a.accepted, a.beta_used);
             } else {
                 // e(0) of Algorithm 2 through Remark 1.
-                const double e2 = st->nx2 - 2.0 * s1 + s2;
-                const double e0 = sqrt(e2 > 0.0 ? e2 : 0.0);
+                double e2 = st->nx2 - 2.0 * s1 + s2;
+                if (st->e2_scale_n > 0) e2 *= st->e2_scale[0];
+                const double e0 = err_of_sq(e2);
                 a.trace[0] = e0 / sqrt(st->nx2);
                 st->e0 = e0;
                 st->e_prev = e0;

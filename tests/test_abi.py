@@ -130,3 +130,30 @@ def test_batch_parameter_validation(kw):
         P.Batch(**args)
     assert e.value.status == P.Status.E_INVAL
 
+
+
+def test_error_scale_hook_validates_before_device_work():
+    import ctypes as C
+    lib = P.lib()
+    sc = np.array([1.0, np.nan])
+    assert lib.nmf_set_error_scale(None, sc.ctypes.data, 2) == P.Status.E_INVAL
+
+
+@pytest.mark.parametrize("bad,what", [
+    ("f16", "float32"), ("bf16", "float32"), ("shape", "shape"), ("small", "shape"),
+    ("strided", "contiguous"), ("cpu", "cuda"), ("numpy", "torch tensor")])
+def test_device_tensor_checks_reject_before_any_launch(bad, what):
+    """Raw device pointers go to the kernels as m x r and r x n FP32 arrays:
+    the binding must refuse anything that is not exactly that."""
+    torch = pytest.importorskip("torch")
+    from paper_1805_06604_amd.binding import _check_device_tensor
+    m, r = 6, 3
+    t = {"f16": torch.zeros(m, r, dtype=torch.float16),
+         "bf16": torch.zeros(m, r, dtype=torch.bfloat16),
+         "shape": torch.zeros(r, m),
+         "small": torch.zeros(m - 1, r),
+         "strided": torch.zeros(r, m).t(),
+         "cpu": torch.zeros(m, r),
+         "numpy": np.zeros((m, r), np.float32)}[bad]
+    with pytest.raises(ValueError, match=what):
+        _check_device_tensor(t, (m, r), "W0", 0)

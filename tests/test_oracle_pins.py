@@ -254,6 +254,86 @@ def test_alg2_pipeline_against_brute_force(hp):
     np.testing.assert_allclose(out["H"], H, atol=1e-8)
 
 
+def _alg2_brute_deciding(X, W0, H0, hp, e2_scale, beta0=0.5, gamma=1.05,
+                        gamma_bar=1.01, eta=1.5):
+    """The brute-force pipeline of _alg2_brute taking its own decisions, as
+    Algorithm 2 states them: restart when e(k) is not finite or exceeds the
+    previous finite error (R7, R9), accept otherwise (ties accept, R8).
+    e(k)^2 is multiplied by e2_scale[k] first (the oracle's test hook). The
+    beta of each iteration comes from the pinned Algorithm 3 script fed with
+    the decisions taken so far."""
+    W, H = W0.copy(), H0.copy()
+    Wy, Hy = W.copy(), H.copy()
+    nx = np.linalg.norm(X)
+    e_prev = np.sqrt(np.sum((X - W @ H) ** 2) * e2_scale[0])
+    trace, decisions = [e_prev / nx], []
+    for k in range(1, len(e2_scale)):
+        bu, _ = oracle.beta_script(decisions + [1], beta0, gamma, gamma_bar, eta)
+        beta = bu[-1]
+        Hn = np.stack([brute_force_nnls(Wy, X[:, c]) for c in range(X.shape[1])], 1)
+        Hyn = Hn + beta * (Hn - H)
+        if hp == 3:
+            Hyn = np.maximum(Hyn, 0.0)
+        Hw = Hn if hp == 1 else Hyn
+        Wn = np.stack([brute_force_nnls(Hw.T, X[i, :]) for i in range(X.shape[0])], 0)
+        Wyn = Wn + beta * (Wn - W)
+        e2 = np.sum((X - Wn @ Hw) ** 2) * e2_scale[k]
+        e = np.sqrt(e2) if np.isfinite(e2) else abs(e2)
+        trace.append(e / nx)
+        acc = bool(np.isfinite(e) and e <= e_prev)
+        decisions.append(int(acc))
+        if acc:
+            W, H, Wy, Hy = Wn, Hn, Wyn, Hyn
+        else:
+            Wy, Hy = W.copy(), H.copy()
+        if np.isfinite(e):
+            e_prev = e
+    return np.array(trace), np.array(decisions, dtype=bool), W, H
+
+
+@pytest.mark.parametrize("flags", [0, oracle.ERR_REMARK1])
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_error_restarts_and_keeps_the_previous_error(flags, bad):
+    """R9 against the brute-force pipeline deciding for itself: a non-finite
+    e(2) must be a restart, and must not become the error that e(3) is
+    compared with. e(3)^2 is inflated a millionfold, so it exceeds e(1) and
+    must restart too; had e(2) replaced e(1), nothing would exceed it and
+    iteration 3 would be accepted. The error by Remark 1 (which clamps a
+    slightly negative e^2 at zero) must not turn a NaN into an error of 0."""
+    rng = np.random.default_rng(11)
+    m, n, r = 6, 5, 2
+    X = rng.random((m, n))
+    W0 = rng.random((m, r))
+    H0 = rng.random((r, n))
+    scale = np.array([1.0, 1.0, bad, 1e6, 1.0, 1.0])
+    out = oracle.solve(X, r, W0, H0, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
+                       eta=1.5, inner_k=3000, max_iter=5, flags=flags, e2_scale=scale)
+    tr, dec, W, H = _alg2_brute_deciding(X, W0, H0, 3, scale)
+    assert list(dec[:3]) == [True, False, False]
+    np.testing.assert_array_equal(out["accepted"], dec)
+    assert not np.isfinite(out["trace"][2]) and not np.isfinite(tr[2])
+    if bad == np.inf:
+        assert out["trace"][2] == np.inf
+    else:
+        assert np.isnan(out["trace"][2])
+    fin = np.isfinite(tr)
+    np.testing.assert_allclose(out["trace"][fin], tr[fin], rtol=1e-8)
+    # Alg. 3 for accept, restart, restart, then the pipeline's outcomes.
+    np.testing.assert_allclose(out["beta"][:4], [0.5, 0.525, 0.35, 0.35 / 1.5], rtol=1e-15)
+    np.testing.assert_allclose(out["W"], W, atol=1e-8)
+    np.testing.assert_allclose(out["H"], H, atol=1e-8)
+
+
+@pytest.mark.parametrize("flags", [0, oracle.ERR_REMARK1])
+def test_nonfinite_initial_error_is_a_numeric_error(flags):
+    """R9: a non-finite e(0) is reported (status ORACLE_ENUMERIC), not
+    taken as an error of 0."""
+    p = S.fullrank(2, m=20, n=15, r=3)
+    for bad in (np.nan, np.inf):
+        with pytest.raises(RuntimeError, match="status 2"):
+            oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=3, flags=flags, e2_scale=[bad])
+
+
 def test_all_restarts_keep_the_initial_iterate():
     p = S.fullrank(2, m=20, n=15, r=3)
     out = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=5, replay=[0] * 5)
@@ -628,3 +708,17 @@ def test_adaptive_replay_of_own_sweep_counts_is_identical():
     np.testing.assert_array_equal(a["trace"], b["trace"])
     np.testing.assert_array_equal(a["sweeps"], b["sweeps"])
     assert np.all(a["sweep_margin"][a["sweeps"] >= 2] > 0)
+
+
+@pytest.mark.parametrize("flag", [oracle.ROUND_F32, oracle.ROUND_F32_RZ])
+def test_fp32_storage_probes_store_fp32_values_near_the_fp64_run(flag):
+    """The conditioning probes of the parity protocol: every stored iterate
+    is an FP32 value, and over a few iterations the run stays within a few
+    FP32 units of the FP64 run (they perturb, they do not change the method)."""
+    p = S.fullrank(6, m=30, n=25, r=4)
+    a = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=5)
+    b = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=5, flags=flag, replay=a["accepted"])
+    for key in ("W", "H"):
+        np.testing.assert_array_equal(b[key], b[key].astype(np.float32).astype(np.float64))
+        assert 0 < np.abs(b[key] - a[key]).max() < 1e-4 * np.abs(a[key]).max()
+    np.testing.assert_allclose(b["trace"], a["trace"], rtol=1e-5)
