@@ -74,7 +74,8 @@ typedef enum { NMF_INNER_FIXED = 0, NMF_INNER_EXACT = 1, NMF_INNER_ADAPTIVE = 2 
 
 /* How the two O(mnr) products X^T W and X H^T are computed. Whatever the
  * choice, the products are summed over K-chunks in FP64, and the HALS sweeps,
- * Grams and objective run in FP64 on FP32-stored W and H.
+ * Grams and objective run in FP64 on FP32-stored W and H. MFMA_FAST needs
+ * X stored in 16 bits (NMF_E_UNSUPPORTED for FP32 X and for sparse X).
  *   AUTO       : MFMA_EXACT for FP32 X, MFMA_FAST for BF16 and FP16 X.
  *   VALU       : FP64 FMA on the vector ALUs (exact products of the stored
  *                values, FP64 sums): the reference-accuracy path, slowest.

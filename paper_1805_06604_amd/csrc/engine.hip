@@ -27,7 +27,7 @@ struct nmf_ctx {
     int64_t ldx = 0, ldxt = 0;
     int *zexp_x = nullptr;   // exact-integer path: row scale exponents of X
     int *zexp_xt = nullptr;  // and of X^T
-    int prod_kernel = nmf::PK_MFMA_L2;
+    int prod_kernel = nmf::PK_MFMA_I8;
     nmf::ProdArgs pa{};  // A = X H_w^T
     nmf::ProdArgs pc{};  // C^T = X^T W_y
     nmf::CsrPlan csr_x{};    // sparse X: CSR of X (for A) and of X^T (for C^T)
@@ -86,7 +86,7 @@ int choose_kernel(const nmf_params *p, int fmt)
     switch (p->prod) {
     case NMF_PROD_VALU: return nmf::PK_VALU;
     case NMF_PROD_MFMA_EXACT: return nmf::PK_MFMA_I8;
-    case NMF_PROD_MFMA_FAST: return p->x_dtype == NMF_X_F32 ? nmf::PK_MFMA_L1 : nmf::PK_MFMA_X16;
+    case NMF_PROD_MFMA_FAST: return nmf::PK_MFMA_X16;
     default: return p->x_dtype == NMF_X_F32 ? nmf::PK_MFMA_I8 : nmf::PK_MFMA_X16;
     }
 }
@@ -636,6 +636,10 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
     if (X->fmt == NMF_CSR && (p->x_dtype != NMF_X_F32 || p->prod == NMF_PROD_MFMA_FAST))
         return fail(nullptr, NMF_E_UNSUPPORTED,
                     "sparse X is kept in FP32 with FP64 sums: x_dtype must be F32 and prod not MFMA_FAST");
+    if (X->fmt != NMF_CSR && p->x_dtype == NMF_X_F32 && p->prod == NMF_PROD_MFMA_FAST)
+        return fail(nullptr, NMF_E_UNSUPPORTED,
+                    "MFMA_FAST streams X in 16 bits: it needs x_dtype BF16 or F16 "
+                    "(FP32 X uses MFMA_EXACT or VALU)");
 
     nmf_ctx *c = new (std::nothrow) nmf_ctx();
     if (!c) return fail(nullptr, NMF_E_NOMEM, "host allocation failed");

@@ -188,11 +188,6 @@ hipError_t launch(int rp, int xdtype, const ProdArgs &a, hipStream_t s, hipEvent
 namespace csr {
 hipError_t launch(int rp, const ProdArgs &a, hipStream_t s);
 }
-namespace mfma {
-void launch_f32(int rp, int L, const ProdArgs &a, hipStream_t s);
-void launch_bf16(int rp, int L, const ProdArgs &a, hipStream_t s);
-void launch_f16(int rp, int L, const ProdArgs &a, hipStream_t s);
-}  // namespace mfma
 
 hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hipStream_t s,
                           hipEvent_t mid)
@@ -214,14 +209,7 @@ hipError_t launch_product(int rp, int xdtype, int kernel, const ProdArgs &a, hip
         default: return hipErrorInvalidValue;
         }
     }
-    const int L = (kernel == PK_MFMA_L2) ? 2 : 1;
-    switch (xdtype) {
-    case 0: mfma::launch_f32(rp, L, a, s); break;
-    case 1: mfma::launch_bf16(rp, L, a, s); break;
-    case 2: mfma::launch_f16(rp, L, a, s); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_convert_x(const float *src, int64_t m, int64_t n, int xdtype, void *X,

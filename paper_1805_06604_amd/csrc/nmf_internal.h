@@ -152,13 +152,12 @@ struct ProdArgs {
     const CsrPlan *csr;
 };
 
-// Product kernels: VALU FP64 FMA over FP32 operands (products exact, sums in
-// FP64), or matrix cores with operands split into BF16 parts keeping the part
-// pairs of relative weight >= 2^-8 (L = 1) or >= 2^-16 (L = 2), summed in
-// FP32 within a K-chunk (PK_MFMA_X16: the L = 1 product for 16-bit X stored
-// in fragment order, with the factor split once per product).
-enum ProdKernel { PK_VALU = 0, PK_MFMA_L1 = 1, PK_MFMA_L2 = 2, PK_MFMA_I8 = 3, PK_CSR = 4,
-                  PK_MFMA_X16 = 5 };
+// Product kernels: VALU FP64 FMA over the stored values (products exact, sums
+// in FP64); the exact-integer matrix-core product (X and the factor in int8
+// slices, int32 sums); the sparse product; and the 16-bit X product on the
+// BF16 matrix cores (X in fragment order, the factor split into two BF16
+// parts once per product, FP32 sums within a K-chunk).
+enum ProdKernel { PK_VALU = 0, PK_MFMA_I8 = 3, PK_CSR = 4, PK_MFMA_X16 = 5 };
 
 // Device buffers of one context. Factors are FP32, row-major with RP columns
 // (r rounded up to a multiple of 16; the padding stays zero):

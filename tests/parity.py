@@ -10,8 +10,10 @@ case, each measured on the oracle itself and never on the GPU result:
   * Conditioning. W and H are stored in FP32. The oracle is rerun twice
     with its iterates rounded to FP32 after every update (all arithmetic
     still FP64), to nearest and toward zero: two independent perturbations
-    of the size FP32 storage makes. d_f32 is the larger of the two reruns'
-    moves; on chaotic trajectories it exceeds the targets. The bound becomes
+    of the size FP32 storage makes. d_f32 is the largest distance among the
+    three runs (each rerun from the FP64 run, and the two reruns from each
+    other: two FP32-storage implementations of the same method); on chaotic
+    trajectories it exceeds the targets. The bound becomes
     max(target, 3 d_f32), for the factors and for each trace entry.
     The drift of a chaotic trajectory grows with k, so each entry takes the
     largest drift seen up to its iteration.
@@ -109,7 +111,8 @@ def compare_to_oracle(p, gpu, max_iter, trace_iters=50, oracle_flags=0, pair=Non
     k = min(trace_iters, gpu.n_iter) + 1
     ro, rg = ref["trace"][:k], gpu.trace[:k]
     with np.errstate(invalid="ignore", divide="ignore"):
-        d_tr = np.max([np.abs(q["trace"][:k] - ro) / ro for q in probes], axis=0)
+        d_tr = np.max([np.abs(q["trace"][:k] - ro) / ro for q in probes]
+                      + [np.abs(probes[0]["trace"][:k] - probes[1]["trace"][:k]) / ro], axis=0)
         d_env = np.fmax.accumulate(np.where(np.isfinite(d_tr), d_tr, 0.0))
         tr_tol = np.maximum(TRACE_RTOL, 3 * d_env)
         rel = np.abs(rg - ro) / ro
@@ -125,7 +128,8 @@ def compare_to_oracle(p, gpu, max_iter, trace_iters=50, oracle_flags=0, pair=Non
               f"k={idx.tolist()[:8]}, max |rho_g^2 - rho_o^2| = "
               f"{np.abs(rg[idx] ** 2 - ro[idx] ** 2).max():.2e}", flush=True)
     rel = np.where(fin, rel, 0.0)
-    d_f32 = max(max(rel_fro(q["W"], ref["W"]), rel_fro(q["H"], ref["H"])) for q in probes)
+    d_f32 = max(max(rel_fro(a["W"], b["W"]), rel_fro(a["H"], b["H"]))
+                for a, b in [(probes[0], ref), (probes[1], ref), (probes[0], probes[1])])
     fac_tol = max(FACTOR_RTOL, 3 * d_f32)
     dw, dh = rel_fro(gpu.W, ref["W"]), rel_fro(gpu.H, ref["H"])
     dwh = rel_fro(np.asarray(gpu.W, np.float64) @ np.asarray(gpu.H, np.float64),

@@ -157,3 +157,11 @@ def test_device_tensor_checks_reject_before_any_launch(bad, what):
          "numpy": np.zeros((m, r), np.float32)}[bad]
     with pytest.raises(ValueError, match=what):
         _check_device_tensor(t, (m, r), "W0", 0)
+
+
+def test_fast_product_needs_16bit_storage():
+    X = np.ones((4, 3), np.float32)
+    with pytest.raises(P.NMFError) as e:
+        P.Solver(X, 1, prod=P.Prod.MFMA_FAST)
+    assert e.value.status == P.Status.E_UNSUPPORTED
+    assert "16 bits" in str(e.value)
