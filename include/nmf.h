@@ -195,6 +195,39 @@ nmf_status nmf_read(nmf_ctx *ctx, float *W, float *H, int32_t on_device,
                     double *trace, int32_t trace_cap, int32_t *n_iter,
                     uint8_t *accepted, double *beta, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of nmf_create + nmf_solve for dense FP32 X with the exact-integer products
+ * and the fixed inner rule, given and returning device arrays only, with no
+ * device allocation at all. Its working buffers (the int8 slices of X and
+ * X^T, the factor slots, Grams, partial products, the solver state) are
+ * carved from one static device array of 128 MiB held by the library on each
+ * GPU it runs on until the process ends (a solve needs about 16 m n bytes
+ * for X and its copies plus the factor and product buffers, e.g. 95 MiB at
+ * m = n = 2048, r = 40; larger problems are refused with NMF_E_NOMEM). Results are
+ * those of nmf_solve on the same input, bit for bit.
+ *   X (m*n, row-major), W0 (m*r), H0 (r*n): device inputs (W0, H0 >= 0).
+ *   W (m*r), H (r*n): device outputs, the last accepted iterate.
+ *   trace (device, >= max_iter + 1 doubles): rho(0..n_iter) as for nmf_solve;
+ *   accepted (device, >= max_iter bytes) and beta (device, >= max_iter
+ *   doubles) are nullable. info (device, 2 int32): info[0] = NMF_OK, or
+ *   NMF_E_INVAL for a zero or non-finite X or a negative or non-finite W0 or
+ *   H0, or NMF_E_NUMERIC for a non-finite e(0) (no iteration runs then);
+ *   info[1] = the completed iterations.
+ * Every step is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ * and the call returns without waiting; the outputs are valid once the
+ * stream reaches them. Every call on a GPU uses that GPU's one array, and
+ * the array keeps the last call's contents: calls that overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller.
+ * Errors (returned, nothing enqueued): NMF_E_INVAL (parameters, NULL
+ * pointers, m or n < 1), NMF_E_UNSUPPORTED (other x_dtype, prod or inner
+ * rule; flags other than the two readings), NMF_E_NOMEM (beyond the static
+ * array), NMF_E_DEVICE. Messages: nmf_last_error(NULL). */
+nmf_status nmf_solve_noalloc(const float *X, int64_t m, int64_t n, const nmf_params *p,
+                             const float *W0, const float *H0, float *W, float *H,
+                             double *trace, uint8_t *accepted, double *beta, int32_t *info,
+                             void *stream);
+
 /* Test hook of the restart branch of Algorithm 2 (reading: a non-finite
  * e(k) is a restart and does not replace the previous error; a non-finite
  * e(0) is NMF_E_NUMERIC). From the next nmf_start (or nmf_solve) on, the

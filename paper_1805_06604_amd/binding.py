@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libnmf.so")
 EXPORTS = ("nmf_params_default", "nmf_create", "nmf_solve", "nmf_start",
            "nmf_iterate", "nmf_read", "nmf_profile", "nmf_destroy",
            "nmf_last_error", "nmf_read_beta_star", "nmf_read_sweeps", "nmf_set_error_scale",
+           "nmf_solve_noalloc",
            "nmf_batch_create", "nmf_batch_submit", "nmf_batch_step",
            "nmf_batch_result", "nmf_batch_destroy")
 
@@ -134,6 +135,8 @@ def lib():
         L.nmf_read_sweeps.restype = i32
         L.nmf_set_error_scale.argtypes = [p, p, i32]
         L.nmf_set_error_scale.restype = i32
+        L.nmf_solve_noalloc.argtypes = [p, C.c_int64, C.c_int64, p, p, p, p, p, p, p, p, p, p]
+        L.nmf_solve_noalloc.restype = i32
         L.nmf_batch_create.argtypes = [p, p]
         L.nmf_batch_create.restype = i32
         L.nmf_batch_submit.argtypes = [p, p, p, p, p, p]
@@ -361,6 +364,40 @@ def solve(X, r, W0, H0, **params) -> Result:
     """One-shot solve: create a context, run nmf_solve, destroy it."""
     with Solver(X, r, **params) as s:
         return s.solve(W0, H0)
+
+
+def solve_noalloc(X, r, W0, H0, W, H, trace, info, accepted=None, beta=None, stream=None,
+                  **params):
+    """nmf_solve_noalloc on torch CUDA tensors: X (m, n), W0 (m, r), H0 (r, n)
+    float32 inputs; W (m, r), H (r, n) float32, trace (>= max_iter + 1)
+    float64, info (2,) int32 and the optional accepted (uint8) and beta
+    (float64, >= max_iter each) outputs, all on the current device. Enqueues
+    the solve on `stream` and returns without waiting."""
+    import torch
+    prm = make_params(r, **params)
+    m, n = int(X.shape[0]), int(X.shape[1])
+    dev = _current_device()
+    _check_device_tensor(X, (m, n), "X", dev)
+    for t, shape, name in ((W0, (m, r), "W0"), (H0, (r, n), "H0"), (W, (m, r), "W"),
+                           (H, (r, n), "H")):
+        _check_device_tensor(t, shape, name, dev)
+    iters = max(prm.max_iter, 1)
+    for t, dt, size, name in ((trace, torch.float64, prm.max_iter + 1, "trace"),
+                              (info, torch.int32, 2, "info"),
+                              (accepted, torch.uint8, iters, "accepted"),
+                              (beta, torch.float64, iters, "beta")):
+        if t is None and name in ("accepted", "beta"):
+            continue
+        if (t is None or t.dtype != dt or not t.is_cuda or t.device.index != dev
+                or not t.is_contiguous() or t.numel() < size):
+            raise ValueError(f"{name} must be a contiguous {dt} tensor of at least {size} "
+                             f"entries on cuda:{dev}")
+    ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+    st = lib().nmf_solve_noalloc(ptr(X), m, n, C.byref(prm), ptr(W0), ptr(H0), ptr(W), ptr(H),
+                                 ptr(trace), ptr(accepted), ptr(beta), ptr(info),
+                                 _stream(stream))
+    if st != Status.OK:
+        raise NMFError(st, lib().nmf_last_error(None).decode())
 
 
 class _BatchParams(C.Structure):

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnmf.so")
 SOURCES = ["sweep_rp64.hip", "sweep_rp48.hip", "sweep_rp32.hip", "sweep_rp16.hip",
            "prod_i8.hip", "prod_x16.hip", "prod_csr.hip",
-           "engine.hip", "batch.hip", "kernels_sweep.hip", "kernels_dense.hip"]
+           "engine.hip", "batch.hip", "noalloc.hip", "kernels_sweep.hip", "kernels_dense.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
