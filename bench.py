@@ -61,9 +61,11 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2048,
                     help="m = n of the oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-full", type=int, default=1,
+                    help="1: also time one oracle iteration on the full benchmark problem")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run the 1 GiB reference copy (counter calibration) first")
-    ap.add_argument("--serve-requests", type=int, default=512,
+    ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the batched-serving measurement (0 disables)")
     ap.add_argument("--serve-qps", type=float, default=2000.0,
                     help="Poisson arrival rate of the serving stream")
@@ -74,8 +76,8 @@ def parse():
                     help="batch iterations between completion checks")
     ap.add_argument("--serve-qps-low", type=float, default=100.0,
                     help="second arrival rate, below saturation (0: skip)")
-    ap.add_argument("--x16-steps", type=int, default=50,
-                    help="timed steps of the 16-bit X runs (BF16, FP16; 0: skip)")
+    ap.add_argument("--x16", type=int, default=1,
+                    help="1: time the same run with X stored in BF16 and in FP16")
     ap.add_argument("--workload-steps", type=int, default=50,
                     help="timed iterations on each of the other configurations (0: skip)")
     ap.add_argument("--workload-oracle", type=int, default=1,
@@ -112,24 +114,44 @@ def measured_traffic(workload_key, kind="i8"):
     return rec.get("bytes_per_launch")
 
 
-def oracle_flops(m, n, r, K):
-    """Flops of one oracle iteration: two products and the explicit residual
-    (2mnr each) plus the sweeps and Grams."""
-    return 6.0 * m * n * r + 2.0 * (K + 1) * (m + n) * r * r
+def residual_fp64(X, W, H, block=1024):
+    """||X - W H||_F / ||X||_F of the returned factors against the FP32 X,
+    in FP64 on the host, a block of rows at a time."""
+    W = np.asarray(W, np.float64)
+    H = np.asarray(H, np.float64)
+    num = den = 0.0
+    for i in range(0, X.shape[0], block):
+        Xb = X[i:i + block].astype(np.float64)
+        R = Xb - W[i:i + block] @ H
+        num += float(np.vdot(R, R))
+        den += float(np.vdot(Xb, Xb))
+    return float(np.sqrt(num / den))
 
 
-def cpu_baseline(args):
+def cpu_baseline(args, p_full):
+    """The FP64 oracle as it stands (single thread), error by Remark 1 as on
+    the GPU: one outer iteration of the full benchmark problem, timed as the
+    difference of a solve with one iteration and a solve with none (which
+    costs the set-up and e(0)); and a few iterations at the smaller sample
+    size. The full-size figure is the value."""
     import nmf_synth as S
     import oracle
+    kw = dict(hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
+              inner_k=args.inner_k, flags=oracle.ERR_REMARK1)
     s = args.cpu_sample
     p = S.planted(0, m=s, n=s, r=args.r)
-    kw = dict(hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
-              inner_k=args.inner_k)
     t0 = time.perf_counter()
     oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=args.cpu_iters, **kw)
-    t = time.perf_counter() - t0
-    scale = oracle_flops(args.m, args.n, args.r, args.inner_k) / oracle_flops(s, s, args.r, args.inner_k)
-    per_iter_full = t / args.cpu_iters * scale
+    t_small = time.perf_counter() - t0
+    t_full = None
+    if args.cpu_full and p_full is not None:
+        q = p_full
+        t0 = time.perf_counter()
+        oracle.solve(q.X, q.r, q.W0, q.H0, max_iter=0, **kw)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.solve(q.X, q.r, q.W0, q.H0, max_iter=1, **kw)
+        t_full = time.perf_counter() - t0 - t_setup
     cpu = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -139,18 +161,28 @@ def cpu_baseline(args):
                     break
     except OSError:
         pass
-    out = {"value": 1.0 / per_iter_full, "unit": "iters/s", "cores": 1, "kind": "oracle",
-           "sample": (f"FP64 oracle (single thread), {args.cpu_iters} iterations of the planted "
-                      f"workload at {s}x{s}, r={args.r}, K={args.inner_k} took {t:.2f} s; scaled "
-                      f"to {args.m}x{args.n} by the flop ratio {scale:.1f}; host {cpu}, "
-                      f"os.cpu_count()={os.cpu_count()}")}
+    host = f"host {cpu}, os.cpu_count()={os.cpu_count()}, one thread"
+    if t_full is not None:
+        out = {"value": 1.0 / t_full, "unit": "iters/s", "cores": 1, "kind": "oracle",
+               "sample": (f"FP64 oracle, error by Remark 1: one outer iteration of the planted "
+                          f"{args.m}x{args.n}, r={args.r}, K={args.inner_k} workload took "
+                          f"{t_full:.1f} s (a one-iteration solve minus the set-up and e(0) of a "
+                          f"zero-iteration solve); {host}"),
+               "seconds_per_iter_full": t_full}
+    else:
+        out = {"value": None, "unit": "iters/s", "cores": 1, "kind": "oracle",
+               "sample": "full-size oracle iteration not run (--cpu-full 0)"}
+    out["small_sample"] = {"workload": f"planted {s}x{s}, r={args.r}, K={args.inner_k}",
+                           "iters": args.cpu_iters, "seconds": t_small,
+                           "iters_per_s": args.cpu_iters / t_small}
     if args.workload_oracle and args.workload_steps > 0:
         # The oracle on the same problems as the workloads leg, a few iterations each.
         cfg = {}
         for name, make, iters in workload_specs(S):
             p = make()
             t0 = time.perf_counter()
-            oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=iters, **WORKLOAD_PARAMS)
+            oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=iters, flags=oracle.ERR_REMARK1,
+                         **WORKLOAD_PARAMS)
             t = time.perf_counter() - t0
             cfg[name] = {"iters_per_s": iters / t, "iters": iters, "seconds": t}
         out["workloads"] = cfg
@@ -161,12 +193,15 @@ FP64_VECTOR_PEAK_TFS = 78.6
 
 
 def nnls_flops(F, r):
-    """Algorithmic flops of the exact NNLS of every row of F (rows x r) with
-    final passive set the row's support, p entries: one Cholesky of the
-    passive system (p^3/3 FMA), two triangular solves (p^2) and the dual
-    check off the passive set ((r - p) p)."""
+    """Flops of the exact NNLS as the solve's usual route does it, per row
+    with final support p (q = r - p coordinates held at zero): z = G^-1 c
+    with the shared inverse (2 r^2), the q x q system of the held
+    coordinates ((2/3) q^3) and the rank-q correction of z (2 r q). The
+    inverse itself (2 r^3 once per side) and pivoting steps that end on
+    another support are not counted."""
     p = np.count_nonzero(np.asarray(F) > 0, axis=1).astype(np.float64)
-    return float(np.sum(2.0 * (p ** 3 / 3.0 + p * p + (r - p) * p)))
+    q = r - p
+    return float(np.sum(2.0 * r * r + (2.0 / 3.0) * q ** 3 + 2.0 * r * q))
 
 
 def eanls(args, P, p, stream, torch):
@@ -190,14 +225,18 @@ def eanls(args, P, p, stream, torch):
     res = solver.read(stream=stream)
     solver.close()
     # The exact-solve phases include the no-sweep epilogue launch after the
-    # solve kernel; the flops are those of the final supports.
+    # solve kernel; the flops are those of the usual route on the final
+    # supports. The solve waits on chains of dependent LDS broadcasts and
+    # FP64 divisions (pivoting steps), so it is latency-bound: the flop rate
+    # is reported against the FP64 peak only for scale.
     solve_ms = ph["sweep_h"] + ph["sweep_w"]
     flops = nnls_flops(res.H.T, r) + nnls_flops(res.W, r)
     achieved = flops / (solve_ms * 1e-3) / 1e12
     return {"workload": f"planted dense {m}x{n} r={r}, E-ANLS hp=1 beta0=0.5 eta=1.5 gamma=1.1 "
                         f"gamma_bar=1.05", "value": 1e3 / ms, "unit": "iters/s", "ms_per_step": ms,
             "steps": args.eanls_steps, "phase_ms": ph, "rho_final": float(res.trace[-1]),
-            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFS,
+            "rho_fp64": residual_fp64(p.X, res.W, res.H),
+            "roofline": {"bound": "latency", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFS,
                          "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFS,
                          "traffic": None, "kernel": "exact NNLS solve (both sides per iteration)",
                          "flops_per_iteration": flops, "ms_per_iteration": solve_ms}}
@@ -256,10 +295,11 @@ def variant(args, P, S, p, stream, torch, x_dtype, prod, K, steps, label):
     sx = XBYTES[x_dtype]
     nbytes = (m * n * sx + m * r * 4 + n * r * 8) + (m * n * sx + n * r * 4 + m * r * 8)
     achieved = nbytes / ((ph["prod_ct"] + ph["prod_a"]) * 1e-3) / 1e9
-    return res.trace, {
+    return res, {
         "workload": label, "x_dtype": x_dtype, "prod": prod, "inner_k": K,
         "value": 1e3 / ms, "unit": "iters/s", "ms_per_step": ms, "steps": steps, "phase_ms": ph,
-        "rho_final": float(res.trace[-1]),
+        "iterations": int(res.n_iter), "rho_final": float(res.trace[-1]),
+        "rho_fp64": residual_fp64(p.X, res.W, res.H),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(f"planted_{m}x{n}_r{r}_{x_dtype}_{prod}",
@@ -311,11 +351,23 @@ WORKLOAD_PARAMS = dict(hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01, eta=1.5, inn
 def workload_specs(S):
     return [("C1 low-rank synthetic 200x200 r=10", lambda: S.lowrank(0), 100),
             ("E2 full-rank synthetic 200x200 r=20", lambda: S.fullrank(0), 100),
-            ("C2 image-like dense 10000x2000 r=49", lambda: S.imagelike(0), 2),
-            ("C3 document-like CSR 30000x20000 r=20, nnz 1.8M", lambda: S.doclike(0), 1)]
+            ("C2 image-like dense 10000x2000 r=49", lambda: S.imagelike(0), 5),
+            ("C3 document-like CSR 30000x20000 r=20, nnz 1.8M", lambda: S.doclike(0), 10)]
 
 
-def serving(args, P, S, qps, n_seq):
+def serving_problems(args, S):
+    """The problems of the request stream (the same for every arrival rate:
+    the stream draws sizes and seeds independently of the rate), generated
+    on host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    reqs = S.requests(count=args.serve_requests, qps=1.0, seed=0)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        probs = list(ex.map(S.request_problem, reqs))
+    return probs, time.perf_counter() - t0
+
+
+def serving(args, P, S, qps, n_seq, probs, t_gen):
     """Batched solves of a Poisson stream of small problems (m, n ~
     U{64..2048}, r in {5, 10, 20, 40}, X = max(0, W H + 1% noise)), each run
     to 200 iterations or |rho(k) - rho(k-1)| < 1e-6, replayed in real time:
@@ -323,9 +375,7 @@ def serving(args, P, S, qps, n_seq):
     from arrival to its result on the host. The baseline solves the first
     requests of the same stream one at a time (one context each)."""
     reqs = S.requests(count=args.serve_requests, qps=qps, seed=0)
-    t_gen = time.perf_counter()
-    probs = [S.request_problem(q) for q in reqs]
-    t_gen = time.perf_counter() - t_gen
+    assert all(q.seed == pr.seed and q.m == pr.X.shape[0] for q, pr in zip(reqs, probs))
     kw = dict(max_iter=200, tol=1e-6, hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
               inner_k=args.inner_k)
     lat = [None] * len(reqs)
@@ -463,28 +513,30 @@ def main():
                    "eta": 1.5},
         "hbm_gbs": iter_bytes * args.steps / (ms * 1e-3) / 1e9,
         "phase_ms": phases,
+        "iterations": int(res.n_iter),
         "rho_final": float(res.trace[-1]),
+        "rho_fp64": residual_fp64(p.X, res.W, res.H),
         "accepted": int(res.accepted.sum()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "X-streaming product",
                      "bytes_per_launch": 0.5 * (bytes_ct + bytes_a), "ms_per_launch": prod_ms},
     }
-    # The same run with X stored in 16 bits (matrix-core products on BF16
-    # parts), its final error set against the FP32 run's at the same
-    # iteration; and with one inner sweep per block.
-    if args.x16_steps > 0 and args.x_dtype == "f32":
+    # The same run (same iterations) with X stored in 16 bits (BF16
+    # matrix-core products): its final error against the FP32 X, in FP64,
+    # set against the FP32 run's; and with one inner sweep per block.
+    if args.x16 and args.x_dtype == "f32":
         for xd16 in ("bf16", "f16"):
-            tr, v = variant(args, P, S, p, stream, torch, xd16, "fast", K, args.x16_steps,
-                            f"planted dense {m}x{n} r={r}, X stored as {xd16}, K={K}")
-            k = min(len(tr), len(res.trace)) - 1
-            v["rho_f32_same_iter"] = float(res.trace[k])
-            v["abs_rho_gap_vs_f32"] = float(abs(tr[k] - res.trace[k]))
+            r16, v = variant(args, P, S, p, stream, torch, xd16, "fast", K, args.steps,
+                             f"planted dense {m}x{n} r={r}, X stored as {xd16}, K={K}")
+            v["rho_fp64_f32_run"] = out["rho_fp64"]
+            v["abs_rho_fp64_gap_vs_f32"] = abs(v["rho_fp64"] - out["rho_fp64"])
             out[f"x_{xd16}"] = v
     if args.k1_steps > 0:
         _, v = variant(args, P, S, p, stream, torch, args.x_dtype, args.prod, 1, args.k1_steps,
                        f"planted dense {m}x{n} r={r}, one inner sweep per block (K=1)")
         out["inner_k1"] = v
+    cpu = cpu_baseline(args, p) if args.cpu_sample > 0 else None
     del p
     if ea is not None:
         out["eanls"] = ea
@@ -493,11 +545,14 @@ def main():
     if args.workload_steps > 0:
         out["workloads"] = workloads(args, P, S, stream, torch)
     if args.serve_requests > 0:
-        out["serving"] = serving(args, P, S, args.serve_qps, args.serve_seq)
+        probs, t_gen = serving_problems(args, S)
+        out["serving"] = serving(args, P, S, args.serve_qps, args.serve_seq, probs, t_gen)
         if args.serve_qps_low > 0:
-            out["serving_below_saturation"] = serving(args, P, S, args.serve_qps_low, 0)
-    if args.cpu_sample > 0:
-        out["cpu_baseline"] = cpu_baseline(args)
+            out["serving_below_saturation"] = serving(args, P, S, args.serve_qps_low, 0, probs,
+                                                      t_gen)
+        del probs
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

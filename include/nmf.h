@@ -22,6 +22,7 @@
 #ifndef NMF_H
 #define NMF_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -227,6 +228,28 @@ nmf_status nmf_solve_noalloc(const float *X, int64_t m, int64_t n, const nmf_par
                              const float *W0, const float *H0, float *W, float *H,
                              double *trace, uint8_t *accepted, double *beta, int32_t *info,
                              void *stream);
+
+/* Checkpoint and resume. The state of a started solve between outer
+ * iterations (the accepted iterate, the warm starts and the iterate slots,
+ * their Gram matrices, the beta / beta-bar state and the errors the next
+ * test of Algorithm 2 compares with, the iteration count, and the trace,
+ * decisions and betas so far) as one host byte array, which a context of
+ * the same problem and parameters (same X, r and nmf_params, max_iter
+ * included) loads to continue the solve: nmf_iterate after nmf_load_state
+ * reproduces the uninterrupted solve bit for bit. The array also records
+ * whether the tol rule had stopped the solve.
+ * nmf_state_size: the array's length for ctx.
+ * nmf_save_state: waits for `stream` and the device, then writes the state
+ * after the last completed iteration into buf (cap >= the size).
+ * nmf_load_state: checks that buf was saved by this library for the same
+ * shape, ||X||_F^2, r and parameters, then makes it the context's state on
+ * `stream` (synchronized before returning); nmf_start is not needed.
+ * Errors: NMF_E_INVAL (NULL pointers, small cap, a state of another
+ * problem, parameters or version, a truncated array), NMF_E_STATE
+ * (nmf_save_state before nmf_start), NMF_E_DEVICE. */
+nmf_status nmf_state_size(nmf_ctx *ctx, size_t *bytes);
+nmf_status nmf_save_state(nmf_ctx *ctx, void *buf, size_t cap, void *stream);
+nmf_status nmf_load_state(nmf_ctx *ctx, const void *buf, size_t len, void *stream);
 
 /* Test hook of the restart branch of Algorithm 2 (reading: a non-finite
  * e(k) is a restart and does not replace the previous error; a non-finite

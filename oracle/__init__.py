@@ -31,6 +31,17 @@ class _Matrix(C.Structure):
                 ("col_idx", C.c_void_p), ("val", C.c_void_p)]
 
 
+class _State(C.Structure):
+    _fields_ = [("k", C.c_int), ("W", C.c_void_p), ("H", C.c_void_p),
+                ("Wy", C.c_void_p), ("Hy", C.c_void_p), ("beta", C.c_double),
+                ("betabar", C.c_double), ("beta_prev", C.c_double),
+                ("beta_acc", C.c_double), ("e_prev", C.c_double), ("e_acc", C.c_double),
+                ("rho", C.c_double)]
+
+
+STATE_SCALARS = ("beta", "betabar", "beta_prev", "beta_acc", "e_prev", "e_acc", "rho")
+
+
 class _Params(C.Structure):
     _fields_ = [("hp", C.c_int), ("beta0", C.c_double), ("gamma", C.c_double),
                 ("gamma_bar", C.c_double), ("eta", C.c_double),
@@ -38,7 +49,8 @@ class _Params(C.Structure):
                 ("tol", C.c_double), ("flags", C.c_int),
                 ("replay", C.c_void_p), ("inner_alpha", C.c_double),
                 ("inner_delta", C.c_double), ("sweeps_replay", C.c_void_p),
-                ("e2_scale", C.c_void_p), ("e2_scale_n", C.c_int)]
+                ("e2_scale", C.c_void_p), ("e2_scale_n", C.c_int),
+                ("resume", C.c_void_p), ("save", C.c_void_p)]
 
 
 def lib():
@@ -88,14 +100,19 @@ class _Held:
 
 def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
           eta=1.5, inner_k=10, max_iter=100, tol=0.0, flags=0, replay=None,
-          inner_alpha=0.5, inner_delta=0.1, sweeps_replay=None, e2_scale=None):
+          inner_alpha=0.5, inner_delta=0.1, sweeps_replay=None, e2_scale=None,
+          resume=None, save=False):
     """Run Alg. 2 with Alg. 3 and return a dict with W, H (last accepted),
     trace (rho(0..n_iter)), accepted, beta, margin, beta_star (section 4,
     per iteration), sweeps (HALS sweeps on H and on W per iteration),
     sweep_margin (closest call of each adaptive stop decision) and n_iter.
     sweeps_replay forces the adaptive sweep counts ((max_iter, 2) array).
     e2_scale (test hook): factors applied to e(k)^2 for k = 0, 1, ... before
-    the test of Algorithm 2 (NaN or inf drive its non-finite branch)."""
+    the test of Algorithm 2 (NaN or inf drive its non-finite branch).
+    save=True adds out["state"], the state after the last iteration (a dict:
+    k, W, H, Wy, Hy and the scalars of STATE_SCALARS); resume=<such a dict>
+    continues that solve (trace entries 0..k are then rho(k) at index k and
+    zeros before it)."""
     h = _Held(X)
     W0 = np.ascontiguousarray(W0, dtype=np.float64).reshape(h.m, r)
     H0 = np.ascontiguousarray(H0, dtype=np.float64).reshape(r, h.n)
@@ -121,10 +138,22 @@ def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
     es = None
     if e2_scale is not None:
         es = np.ascontiguousarray(e2_scale, dtype=np.float64).ravel()
+    rs = sv = None
+    keep = []
+    if resume is not None:
+        arrs = [np.ascontiguousarray(resume[key], dtype=np.float64) for key in ("W", "H", "Wy", "Hy")]
+        keep += arrs
+        rs = _State(int(resume["k"]), *[_ptr(a).value for a in arrs],
+                    *[float(resume[key]) for key in STATE_SCALARS])
+    if save:
+        sarr = dict(W=np.empty((h.m, r)), H=np.empty((r, h.n)), Wy=np.empty((h.m, r)),
+                    Hy=np.empty((r, h.n)))
+        sv = _State(0, *[_ptr(sarr[key]).value for key in ("W", "H", "Wy", "Hy")])
     prm = _Params(hp, beta0, gamma, gamma_bar, eta, inner_k, max_iter, tol,
                   flags, None if rp is None else _ptr(rp).value, inner_alpha, inner_delta,
                   None if sr is None else _ptr(sr).value,
-                  None if es is None else _ptr(es).value, 0 if es is None else es.size)
+                  None if es is None else _ptr(es).value, 0 if es is None else es.size,
+                  None if rs is None else C.addressof(rs), None if sv is None else C.addressof(sv))
     nit = C.c_int(0)
     st = lib().oracle_eahals(C.byref(h.s), r, _ptr(W0), _ptr(H0), C.byref(prm),
                              _ptr(W), _ptr(H), _ptr(trace), _ptr(acc),
@@ -133,9 +162,12 @@ def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
     if st != OK:
         raise RuntimeError(f"oracle_eahals failed with status {st}")
     k = nit.value
-    return dict(W=W, H=H, trace=trace[:k + 1], accepted=acc[:k].astype(bool),
-                beta=beta[:k], margin=margin[:k], beta_star=bstar[:k], sweeps=sweeps[:k],
-                sweep_margin=smargin[:k], n_iter=k)
+    out = dict(W=W, H=H, trace=trace[:k + 1], accepted=acc[:k].astype(bool),
+               beta=beta[:k], margin=margin[:k], beta_star=bstar[:k], sweeps=sweeps[:k],
+               sweep_margin=smargin[:k], n_iter=k)
+    if save:
+        out["state"] = dict(k=sv.k, **sarr, **{key: getattr(sv, key) for key in STATE_SCALARS})
+    return out
 
 
 def beta_star(X, Wn, W, Hw):

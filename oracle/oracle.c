@@ -509,6 +509,11 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         return ORACLE_EINVAL;
     const int adaptive = (p->flags & ORACLE_ADAPTIVE_INNER) != 0;
     if (adaptive && !(p->inner_alpha >= 0.0 && p->inner_delta >= 0.0)) return ORACLE_EINVAL;
+    if (p->resume && (p->resume->k < 0 || p->resume->k > p->max_iter || !p->resume->W ||
+                      !p->resume->H || !p->resume->Wy || !p->resume->Hy))
+        return ORACLE_EINVAL;
+    if (p->save && (!p->save->W || !p->save->H || !p->save->Wy || !p->save->Hy))
+        return ORACLE_EINVAL;
     const int64_t m = X->m, n = X->n;
     const int64_t mr = m * r, rn = (int64_t)r * n;
     const double nx2 = frob2(X);
@@ -528,28 +533,48 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         goto done;
     }
 
-    /* Alg. 2, first step: W_y = W, H_y = H, e(0) = ||X - W H||_F. */
-    memcpy(W, W0, sizeof(double) * mr);
-    memcpy(H, H0, sizeof(double) * rn);
-    memcpy(Wy, W, sizeof(double) * mr);
-    memcpy(Hy, H, sizeof(double) * rn);
-    double e0sq;
-    if (p->flags & ORACLE_ERR_REMARK1) {
-        x_ht(X, r, H, A);
-        gram_rows(n, r, H, B);
-        e0sq = remark1_err2(m, r, nx2, W, A, B);
-    } else {
-        e0sq = explicit_err2(X, r, W, H);
-    }
-    const double e0 = err_of_sq(scaled_err2(p, 0, e0sq));
-    if (!isfinite(e0)) { status = ORACLE_ENUMERIC; goto done; }
-    trace[0] = e0 / nx;
-
     beta_state bs;
-    beta_init(&bs, p->beta0);
-    double e_prev = e0, e_acc = e0;
+    double e_prev, e_acc;
+    int k0 = 0;
+    if (p->resume) {
+        /* Continue a saved solve: its iterates, warm starts, beta state and
+         * the errors the next decision compares with. */
+        const oracle_state *rs = p->resume;
+        k0 = rs->k;
+        memcpy(W, rs->W, sizeof(double) * mr);
+        memcpy(H, rs->H, sizeof(double) * rn);
+        memcpy(Wy, rs->Wy, sizeof(double) * mr);
+        memcpy(Hy, rs->Hy, sizeof(double) * rn);
+        bs.beta = rs->beta;
+        bs.betabar = rs->betabar;
+        bs.beta_prev = rs->beta_prev;
+        bs.beta_acc = rs->beta_acc;
+        e_prev = rs->e_prev;
+        e_acc = rs->e_acc;
+        trace[k0] = rs->rho;
+    } else {
+        /* Alg. 2, first step: W_y = W, H_y = H, e(0) = ||X - W H||_F. */
+        memcpy(W, W0, sizeof(double) * mr);
+        memcpy(H, H0, sizeof(double) * rn);
+        memcpy(Wy, W, sizeof(double) * mr);
+        memcpy(Hy, H, sizeof(double) * rn);
+        double e0sq;
+        if (p->flags & ORACLE_ERR_REMARK1) {
+            x_ht(X, r, H, A);
+            gram_rows(n, r, H, B);
+            e0sq = remark1_err2(m, r, nx2, W, A, B);
+        } else {
+            e0sq = explicit_err2(X, r, W, H);
+        }
+        const double e0 = err_of_sq(scaled_err2(p, 0, e0sq));
+        if (!isfinite(e0)) { status = ORACLE_ENUMERIC; goto done; }
+        trace[0] = e0 / nx;
+        beta_init(&bs, p->beta0);
+        e_prev = e0;
+        e_acc = e0;
+    }
     int k = 0;
-    for (k = 1; k <= p->max_iter; ++k) {
+    for (k = k0 + 1; k <= p->max_iter; ++k) {
         const double beta = bs.beta;
 
         /* H_n: NNLS in H with W_y fixed, warm-started at H_y. */
@@ -632,6 +657,21 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         }
     }
     *n_iter = k - 1;
+    if (p->save) {
+        oracle_state *sv = p->save;
+        sv->k = k - 1;
+        memcpy(sv->W, W, sizeof(double) * mr);
+        memcpy(sv->H, H, sizeof(double) * rn);
+        memcpy(sv->Wy, Wy, sizeof(double) * mr);
+        memcpy(sv->Hy, Hy, sizeof(double) * rn);
+        sv->beta = bs.beta;
+        sv->betabar = bs.betabar;
+        sv->beta_prev = bs.beta_prev;
+        sv->beta_acc = bs.beta_acc;
+        sv->e_prev = e_prev;
+        sv->e_acc = e_acc;
+        sv->rho = trace[k - 1];
+    }
 
 done:
     free(Wy); free(Wn); free(Wyn); free(A);

@@ -93,6 +93,17 @@ typedef struct {
     const double  *val;      /* CSR: nonzero values                     */
 } oracle_matrix;
 
+/* The state of a solve between outer iterations (checkpoint / resume).
+ * The arrays are caller-allocated: W, Wy m*r; H, Hy r*n. */
+typedef struct {
+    int     k;                /* completed outer iterations               */
+    double *W, *H;            /* last accepted iterate                    */
+    double *Wy, *Hy;          /* warm starts of iteration k + 1           */
+    double  beta, betabar, beta_prev, beta_acc;   /* Alg. 3 state         */
+    double  e_prev, e_acc;    /* errors the next test compares with (R7)  */
+    double  rho;              /* rho(k), for the tol rule (R12)           */
+} oracle_state;
+
 typedef struct {
     int    hp;                /* 1, 2 or 3 (Alg. 2)                       */
     double beta0, gamma, gamma_bar, eta;  /* Alg. 3                         */
@@ -112,6 +123,11 @@ typedef struct {
                                  infinite factor drives the non-finite
                                  branch of R9                              */
     int e2_scale_n;
+    const oracle_state *resume; /* NULL, or a state saved by an earlier solve
+                                 of the same problem and parameters: the
+                                 solve continues with iteration resume->k + 1
+                                 (trace[0..k] are left as they are)       */
+    oracle_state *save;       /* NULL, or receives the state at the end     */
 } oracle_params;
 
 /* Full solve (Alg. 2 with Alg. 3). Outputs, all caller-allocated:

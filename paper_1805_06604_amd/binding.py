@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libnmf.so")
 EXPORTS = ("nmf_params_default", "nmf_create", "nmf_solve", "nmf_start",
            "nmf_iterate", "nmf_read", "nmf_profile", "nmf_destroy",
            "nmf_last_error", "nmf_read_beta_star", "nmf_read_sweeps", "nmf_set_error_scale",
-           "nmf_solve_noalloc",
+           "nmf_solve_noalloc", "nmf_state_size", "nmf_save_state", "nmf_load_state",
            "nmf_batch_create", "nmf_batch_submit", "nmf_batch_step",
            "nmf_batch_result", "nmf_batch_destroy")
 
@@ -137,6 +137,12 @@ def lib():
         L.nmf_set_error_scale.restype = i32
         L.nmf_solve_noalloc.argtypes = [p, C.c_int64, C.c_int64, p, p, p, p, p, p, p, p, p, p]
         L.nmf_solve_noalloc.restype = i32
+        L.nmf_state_size.argtypes = [p, p]
+        L.nmf_state_size.restype = i32
+        L.nmf_save_state.argtypes = [p, p, C.c_size_t, p]
+        L.nmf_save_state.restype = i32
+        L.nmf_load_state.argtypes = [p, p, C.c_size_t, p]
+        L.nmf_load_state.restype = i32
         L.nmf_batch_create.argtypes = [p, p]
         L.nmf_batch_create.restype = i32
         L.nmf_batch_submit.argtypes = [p, p, p, p, p, p]
@@ -307,6 +313,19 @@ class Solver:
             return
         sc = np.ascontiguousarray(scale, dtype=np.float64).ravel()
         self._check(lib().nmf_set_error_scale(self._ctx, _ptr(sc), sc.size))
+
+    def save_state(self, stream=None) -> bytes:
+        """nmf_save_state: the solver state after the last completed iteration."""
+        size = C.c_size_t()
+        self._check(lib().nmf_state_size(self._ctx, C.byref(size)))
+        buf = C.create_string_buffer(size.value)
+        self._check(lib().nmf_save_state(self._ctx, buf, size.value, _stream(stream)))
+        return buf.raw
+
+    def load_state(self, state: bytes, stream=None):
+        """nmf_load_state: continue a solve from a saved state."""
+        buf = C.create_string_buffer(bytes(state), len(state))
+        self._check(lib().nmf_load_state(self._ctx, buf, len(state), _stream(stream)))
 
     def iterate(self, iters, stream=None):
         self._check(lib().nmf_iterate(self._ctx, int(iters), _stream(stream)))

@@ -858,6 +858,162 @@ nmf_status nmf_read(nmf_ctx *c, float *W, float *H, int32_t on_device, double *t
     return NMF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Header of a saved state: what it was saved from, so that a load into a
+// context of another problem or other parameters is refused.
+struct StateHeader {
+    char magic[8];
+    int32_t version, r, hp, inner_rule, inner_k, x_dtype, prod, flags, max_iter, stopped;
+    int64_t m, n;
+    double beta0, gamma, gamma_bar, eta, tol, inner_alpha, inner_delta, nx2;
+    uint64_t bytes;
+};
+constexpr char kStateMagic[8] = {'N', 'M', 'F', 'S', 'T', 'A', 'T', 'E'};
+constexpr int32_t kStateVersion = 1;
+
+// The device buffers that carry a solve from one iteration to the next: the
+// factor slots, the Gram buffers of the slots (with their inverse diagonals
+// and column maxima), the per-iteration records, and the adaptive loop's
+// sweep counts. Everything else is recomputed within an iteration.
+struct StatePart {
+    void *dev;
+    size_t bytes;
+};
+
+std::vector<StatePart> state_parts(nmf_ctx *c)
+{
+    const int64_t m = c->m, n = c->n, rp = c->rp;
+    const size_t iters = (size_t)std::max(c->p.max_iter, 1);
+    const size_t gs = (size_t)nmf::gram_stride(c->rp);
+    std::vector<StatePart> v = {
+        {c->b.Wf, sizeof(float) * nmf::kSlots * m * rp},
+        {c->b.Hf, sizeof(float) * nmf::kSlots * n * rp},
+        {c->b.GW, sizeof(double) * nmf::kSlots * gs},
+        {c->b.GH, sizeof(double) * gs},
+        {c->b.trace, sizeof(double) * (c->p.max_iter + 1)},
+        {c->b.accepted, iters},
+        {c->b.beta_used, sizeof(double) * iters},
+        {c->b.beta_star, sizeof(double) * (c->p.max_iter + 1)}};
+    if (c->p.inner_rule == NMF_INNER_ADAPTIVE) v.push_back({c->b.sweeps, sizeof(int32_t) * 2 * iters});
+    return v;
+}
+
+size_t state_bytes(nmf_ctx *c)
+{
+    size_t total = sizeof(StateHeader) + sizeof(DevState);
+    for (const StatePart &q : state_parts(c)) total += q.bytes;
+    return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+nmf_status nmf_state_size(nmf_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return fail(c, NMF_E_INVAL, "ctx and bytes must not be NULL");
+    *bytes = state_bytes(c);
+    return NMF_OK;
+}
+
+nmf_status nmf_save_state(nmf_ctx *c, void *buf, size_t cap, void *stream)
+{
+    if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");
+    if (!c->started) return fail(c, NMF_E_STATE, "nmf_save_state before a successful nmf_start");
+    const size_t need = state_bytes(c);
+    if (!buf || cap < need) return fail(c, NMF_E_INVAL, "need a buffer of %zu bytes", need);
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    HIP_TRY(c, hipDeviceSynchronize());
+    char *out = static_cast<char *>(buf);
+    DevState h{};
+    HIP_TRY(c, hipMemcpy(&h, c->b.st, sizeof(h), hipMemcpyDeviceToHost));
+    StateHeader hd{};
+    std::memcpy(hd.magic, kStateMagic, sizeof(hd.magic));
+    hd.version = kStateVersion;
+    hd.r = c->r;
+    hd.hp = c->p.hp;
+    hd.inner_rule = c->p.inner_rule;
+    hd.inner_k = c->p.inner_k;
+    hd.x_dtype = c->p.x_dtype;
+    hd.prod = c->p.prod;
+    hd.flags = c->p.flags;
+    hd.max_iter = c->p.max_iter;
+    hd.stopped = (h.done && h.k < c->p.max_iter) ? 1 : 0;   // by the tol rule
+    hd.m = c->m;
+    hd.n = c->n;
+    hd.beta0 = c->p.beta0;
+    hd.gamma = c->p.gamma;
+    hd.gamma_bar = c->p.gamma_bar;
+    hd.eta = c->p.eta;
+    hd.tol = c->p.tol;
+    hd.inner_alpha = c->p.inner_alpha;
+    hd.inner_delta = c->p.inner_delta;
+    hd.nx2 = c->nx2;
+    hd.bytes = need;
+    std::memcpy(out, &hd, sizeof(hd));
+    std::memcpy(out + sizeof(hd), &h, sizeof(h));
+    size_t off = sizeof(hd) + sizeof(h);
+    for (const StatePart &q : state_parts(c)) {
+        HIP_TRY(c, hipMemcpy(out + off, q.dev, q.bytes, hipMemcpyDeviceToHost));
+        off += q.bytes;
+    }
+    return NMF_OK;
+}
+
+nmf_status nmf_load_state(nmf_ctx *c, const void *buf, size_t len, void *stream)
+{
+    if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");
+    if (!buf || len < sizeof(StateHeader)) return fail(c, NMF_E_INVAL, "not a saved state");
+    const char *in = static_cast<const char *>(buf);
+    StateHeader hd;
+    std::memcpy(&hd, in, sizeof(hd));
+    if (std::memcmp(hd.magic, kStateMagic, sizeof(hd.magic)) != 0 || hd.version != kStateVersion)
+        return fail(c, NMF_E_INVAL, "not a saved state of this library version");
+    const nmf_params &p = c->p;
+    if (hd.m != c->m || hd.n != c->n || hd.r != c->r)
+        return fail(c, NMF_E_INVAL, "the state is of a %lld x %lld, r = %d problem",
+                    (long long)hd.m, (long long)hd.n, hd.r);
+    if (hd.nx2 != c->nx2) return fail(c, NMF_E_INVAL, "the state was saved for another X");
+    if (hd.hp != p.hp || hd.inner_rule != p.inner_rule || hd.inner_k != p.inner_k ||
+        hd.x_dtype != p.x_dtype || hd.prod != p.prod || hd.flags != p.flags ||
+        hd.beta0 != p.beta0 || hd.gamma != p.gamma || hd.gamma_bar != p.gamma_bar ||
+        hd.eta != p.eta || hd.tol != p.tol || hd.inner_alpha != p.inner_alpha ||
+        hd.inner_delta != p.inner_delta)
+        return fail(c, NMF_E_INVAL, "the state was saved with other parameters");
+    DevState h;
+    std::memcpy(&h, in + sizeof(hd), sizeof(h));
+    if (h.k < 0 || h.k > p.max_iter)
+        return fail(c, NMF_E_INVAL, "the state has %d iterations, beyond max_iter = %d", h.k, p.max_iter);
+    if (hd.max_iter != p.max_iter) {
+        // The per-iteration records are sized by max_iter: only equal sizes load.
+        return fail(c, NMF_E_INVAL, "the state was saved with max_iter = %d", hd.max_iter);
+    }
+    const size_t need = state_bytes(c);
+    if (len < need || hd.bytes != need) return fail(c, NMF_E_INVAL, "the state is truncated");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // This context's own device pointers and stop rule.
+    h.e2_scale = c->e2_scale;
+    h.e2_scale_n = c->e2_scale_n;
+    h.max_iter = p.max_iter;
+    h.done = (hd.stopped || h.k >= p.max_iter) ? 1 : 0;
+    c->hs = h;
+    size_t off = sizeof(hd) + sizeof(h);
+    for (const StatePart &q : state_parts(c)) {
+        HIP_TRY(c, hipMemcpyAsync(q.dev, in + off, q.bytes, hipMemcpyHostToDevice, s));
+        off += q.bytes;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->b.st, &c->hs, sizeof(h), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->started = true;
+    c->launched = h.k;
+    return NMF_OK;
+}
+
 nmf_status nmf_read_sweeps(nmf_ctx *c, int32_t *sweeps, int32_t cap, int32_t *n_iter)
 {
     if (!c) return fail(nullptr, NMF_E_INVAL, "ctx is NULL");

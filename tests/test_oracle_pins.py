@@ -722,3 +722,37 @@ def test_fp32_storage_probes_store_fp32_values_near_the_fp64_run(flag):
         np.testing.assert_array_equal(b[key], b[key].astype(np.float32).astype(np.float64))
         assert 0 < np.abs(b[key] - a[key]).max() < 1e-4 * np.abs(a[key]).max()
     np.testing.assert_allclose(b["trace"], a["trace"], rtol=1e-5)
+
+
+@pytest.mark.parametrize("hp,kw", [(3, {}), (1, {}), (2, dict(beta0=0.9, gamma=1.1)),
+                                   (3, dict(flags=oracle.EXACT_NNLS)),
+                                   (3, dict(flags=oracle.ADAPTIVE_INNER, inner_k=8))])
+def test_resume_from_a_saved_state_is_bitwise_uninterrupted(hp, kw):
+    """Checkpoint / resume: a solve stopped after 17 iterations and resumed
+    from its saved state reproduces the uninterrupted solve bit for bit
+    (iterates, trace, decisions, betas), restarts included."""
+    p = S.fullrank(7, m=45, n=38, r=6)
+    kw = dict(dict(hp=hp, max_iter=40), **kw)
+    full = oracle.solve(p.X, p.r, p.W0, p.H0, **kw)
+    first = oracle.solve(p.X, p.r, p.W0, p.H0, save=True, **dict(kw, max_iter=17))
+    st = first["state"]
+    assert st["k"] == 17
+    rest = oracle.solve(p.X, p.r, p.W0, p.H0, resume=st, **kw)
+    assert rest["n_iter"] == full["n_iter"] == 40
+    assert (~full["accepted"]).any() or hp == 1, "the case should include restarts"
+    np.testing.assert_array_equal(rest["W"], full["W"])
+    np.testing.assert_array_equal(rest["H"], full["H"])
+    np.testing.assert_array_equal(rest["trace"][17:], full["trace"][17:])
+    np.testing.assert_array_equal(first["trace"], full["trace"][:18])
+    np.testing.assert_array_equal(rest["accepted"][17:], full["accepted"][17:])
+    np.testing.assert_array_equal(rest["beta"][17:], full["beta"][17:])
+
+
+def test_resume_keeps_the_tol_rule():
+    p = S.lowrank(0, m=30, n=30, r=3)
+    full = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=5000, tol=1e-6)
+    k = full["n_iter"]
+    first = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=k - 1, tol=1e-6, save=True)
+    rest = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=5000, tol=1e-6, resume=first["state"])
+    assert rest["n_iter"] == k
+    np.testing.assert_array_equal(rest["W"], full["W"])
