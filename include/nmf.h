@@ -343,7 +343,11 @@ nmf_status nmf_batch_submit(nmf_batch *b, const nmf_matrix *X, const nmf_params 
  * on the host), and returns the numbers of active (admitted ones included),
  * queued and retired-unread problems (each pointer nullable). The set-up of
  * problems admitted while a chunk runs overlaps it; they join at the next
- * chunk. Blocks until the device work is done.
+ * chunk. The last chunk of the call is left running on the device when the
+ * call returns, so that the caller's own work (submissions, reading results)
+ * overlaps it; the next call (or nmf_batch_destroy) waits for it first and
+ * retires the problems it finished, so a result can appear one call later.
+ * Each chunk is one replay of a graph per padded rank, captured once.
  * Errors: NMF_E_INVAL (iters < 1), NMF_E_DEVICE. */
 nmf_status nmf_batch_step(nmf_batch *b, int32_t iters, int32_t *active, int32_t *queued,
                           int32_t *retired);

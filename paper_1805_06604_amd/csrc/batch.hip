@@ -4,11 +4,13 @@
 // Every admitted problem lives in one device arena (first-fit, 256-byte
 // aligned blocks) with the same buffers as a single-problem context. A batch
 // iteration runs one outer iteration of Algorithm 2 for every active problem:
-// per padded rank, eight grouped launches (factor slicing, Xᵀ W_y, H sweeps,
-// H finish, factor slicing, X H_wᵀ, W sweeps, W finish), and before each
-// sweep launch the exact NNLS solves of the E-ANLS problems if there are any,
-// each covering the blocks of all problems of that rank, so that small problems share the chip
-// instead of each paying its own launch latency. A problem that stopped
+// per padded rank, eleven grouped launches (factor slicing, Xᵀ W_y, the
+// exact NNLS solves of the E-ANLS problems, H sweeps, H finish, factor
+// slicing, X H_wᵀ, exact solves, W sweeps, W finish, the decision), each covering the work blocks of
+// all problems of that rank with a fixed grid, so that small problems share
+// the chip instead of each paying its own launch latency. The launches of a
+// rank read their tables from device memory, so one batch iteration (and
+// check_every of them) is captured once as a graph per rank and replayed. A problem that stopped
 // (its device state says done) returns at the entry of every kernel until
 // the host retires it at the next completion check.
 #include "host_util.h"
@@ -35,8 +37,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kClasses = 4;          // padded ranks 16, 32, 48, 64
-constexpr int kKinds = 10;           // grouped kernels of one iteration (8, and the
-                                     // exact NNLS solves of E-ANLS problems, H and W)
+constexpr int kKinds = 11;           // grouped kernels of one iteration (8, the exact
+                                     // NNLS solves of E-ANLS problems, H and W, and
+                                     // the decision after the W finish)
 constexpr int64_t kBatchTargetWG = 64;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -92,7 +95,10 @@ struct Prob {
     int64_t m = 0, n = 0;
     int r = 0, rp = 0;
     int64_t m_pad = 0, n_pad = 0, ldx = 0, ldxt = 0;
-    std::unique_ptr<float[]> X;        // inputs until admitted
+    std::unique_ptr<float[]> X;        // inputs until admitted (pageable), or
+    float *Xpin = nullptr;             // in the batch's pinned pool at pin_off
+    size_t pin_off = 0;
+    const float *xsrc() const { return Xpin ? Xpin : X.get(); }
     std::vector<float> W0, H0;
     size_t off = 0, bytes = 0;         // persistent block
     size_t toff = 0, tbytes = 0;       // admission temporaries
@@ -206,11 +212,19 @@ struct nmf_batch {
     bool dirty = true;
     Entry *d_entries = nullptr;          // kClasses x max_active
     int *d_prefix = nullptr;             // kClasses x kKinds x (max_active + 1)
+    int *d_np = nullptr;                 // kClasses: problems of each padded rank
+    char *pin = nullptr;                 // pinned host pool for submitted X
+    Arena pin_arena;
+    // One batch iteration of a padded rank, and check_every of them, captured
+    // once as graphs on the class streams (their launches read the tables
+    // above, so they stay valid while the active set changes).
+    hipGraphExec_t exec_one[kClasses] = {};
+    hipGraphExec_t exec_chunk[kClasses] = {};
     const DevState **d_states = nullptr; // max_active
     int32_t *d_flags = nullptr;          // 2 x max_active
     int32_t *h_flags = nullptr;          // pinned
     std::vector<Prob *> members[kClasses];
-    int blocks[kClasses][kKinds] = {};
+    bool inflight = false;               // a chunk left running by the last step call
 };
 
 namespace {
@@ -271,7 +285,7 @@ bool admit(nmf_batch *B, Prob &q, nmf_status *err)
     if (e == hipSuccess) e = hipMemsetAsync(B->arena.base + toff, 0, tneed, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b.st, &h, sizeof(h), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(q.src, q.X.get(), sizeof(float) * q.m * q.n, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(q.src, q.xsrc(), sizeof(float) * q.m * q.n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b.stage, q.W0.data(), sizeof(float) * q.m * q.r, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -339,7 +353,6 @@ nmf_status rebuild(nmf_batch *B)
     for (int c = 0; c < kClasses; ++c) {
         const int rp = 16 * (c + 1);
         auto &mem = B->members[c];
-        for (int k = 0; k < kKinds; ++k) B->blocks[c][k] = 0;
         for (size_t i = 0; i < mem.size(); ++i) {
             Prob &q = *mem[i];
             Entry &E = ent[(size_t)c * cap + i];
@@ -359,11 +372,10 @@ nmf_status rebuild(nmf_batch *B)
                                     (int)(q.pa.ld / 64), (int)(q.pa.rows_pad / 128 * q.pa.nsplit),
                                     nmf::sweep::hals_blocks(q.m), nmf::sweep::fin_blocks(rp, 2),
                                     exact ? nmf::sweep::exact_blocks(q.n) : 0,
-                                    exact ? nmf::sweep::exact_blocks(q.m) : 0};
+                                    exact ? nmf::sweep::exact_blocks(q.m) : 0, 1};
             for (int k = 0; k < kKinds; ++k) {
                 int *P = &pre[((size_t)c * kKinds + k) * (cap + 1)];
                 P[i + 1] = P[i] + nb[k];
-                B->blocks[c][k] = P[i + 1];
             }
         }
     }
@@ -372,6 +384,9 @@ nmf_status rebuild(nmf_batch *B)
     BHIP(hipMemcpyAsync(B->d_entries, ent.data(), sizeof(Entry) * ent.size(), hipMemcpyHostToDevice,
                         B->s));
     BHIP(hipMemcpyAsync(B->d_prefix, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice, B->s));
+    int np[kClasses];
+    for (int c = 0; c < kClasses; ++c) np[c] = (int)B->members[c].size();
+    BHIP(hipMemcpyAsync(B->d_np, np, sizeof(np), hipMemcpyHostToDevice, B->s));
     if (!sts.empty())
         BHIP(hipMemcpyAsync(B->d_states, sts.data(), sizeof(DevState *) * sts.size(),
                             hipMemcpyHostToDevice, B->s));
@@ -386,31 +401,71 @@ Group group_of(nmf_batch *B, int c, int kind, size_t member_offset)
     g.base = reinterpret_cast<const char *>(B->d_entries + (size_t)c * B->bp.max_active) + member_offset;
     g.stride = sizeof(Entry);
     g.prefix = B->d_prefix + ((size_t)c * kKinds + kind) * (B->bp.max_active + 1);
-    g.np = (int)B->members[c].size();
+    g.np = B->d_np + c;
     return g;
 }
 
+// Fixed grids of the grouped kernels (workgroups walk the work blocks with a
+// grid stride): about one resident round of the chip per kernel kind.
+constexpr int kGrid[kKinds] = {1024, 256, 512, 1024, 1024, 256, 512, 1024, 512, 512, 512};
+
+// One batch iteration of padded-rank class c on stream cs: both products,
+// the exact solves (a no-op without E-ANLS problems) and both sweep steps.
+nmf_status enqueue_class_iteration(nmf_batch *B, int c, hipStream_t cs)
+{
+    const int rp = 16 * (c + 1);
+    BHIP(nmf::i8::launch_group(rp, group_of(B, c, 0, offsetof(Entry, pc)), kGrid[0],
+                               group_of(B, c, 1, offsetof(Entry, pc)), kGrid[1], cs));
+    BHIP(nmf::launch_group_exact(rp, false, group_of(B, c, 8, offsetof(Entry, hh)), kGrid[8], cs));
+    BHIP(nmf::launch_group_sweep(rp, false, group_of(B, c, 2, offsetof(Entry, hh)), kGrid[2],
+                                 group_of(B, c, 3, offsetof(Entry, fh)), kGrid[3], Group{}, 0, cs));
+    BHIP(nmf::i8::launch_group(rp, group_of(B, c, 4, offsetof(Entry, pa)), kGrid[4],
+                               group_of(B, c, 5, offsetof(Entry, pa)), kGrid[5], cs));
+    BHIP(nmf::launch_group_exact(rp, true, group_of(B, c, 9, offsetof(Entry, hw)), kGrid[9], cs));
+    BHIP(nmf::launch_group_sweep(rp, true, group_of(B, c, 6, offsetof(Entry, hw)), kGrid[6],
+                                 group_of(B, c, 7, offsetof(Entry, fw)), kGrid[7],
+                                 group_of(B, c, 10, offsetof(Entry, fw)), kGrid[10], cs));
+    return NMF_OK;
+}
+
+// Captures `iters` batch iterations of class c into an executable graph.
+nmf_status capture_class(nmf_batch *B, int c, int iters, hipGraphExec_t *out)
+{
+    hipStream_t cs = B->cs[c];
+    BHIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    nmf_status st = NMF_OK;
+    for (int it = 0; it < iters && st == NMF_OK; ++it) st = enqueue_class_iteration(B, c, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st != NMF_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return berr(NMF_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess)
+        return berr(NMF_E_DEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(ei));
+    return NMF_OK;
+}
+
+// Runs `iters` batch iterations of every non-empty class on its stream, as
+// graph launches (check_every iterations per launch, single ones for the rest).
 nmf_status run_iterations(nmf_batch *B, int iters)
 {
-    for (int it = 0; it < iters; ++it)
-        for (int c = 0; c < kClasses; ++c) {
-            if (B->members[c].empty()) continue;
-            const int rp = 16 * (c + 1);
-            const int *nb = B->blocks[c];
-            hipStream_t cs = B->cs[c];
-            BHIP(nmf::i8::launch_group(rp, group_of(B, c, 0, offsetof(Entry, pc)), nb[0],
-                                       group_of(B, c, 1, offsetof(Entry, pc)), nb[1], cs));
-            if (nb[8] > 0)
-                BHIP(nmf::launch_group_exact(rp, false, group_of(B, c, 8, offsetof(Entry, hh)), nb[8], cs));
-            BHIP(nmf::launch_group_sweep(rp, false, group_of(B, c, 2, offsetof(Entry, hh)), nb[2],
-                                         group_of(B, c, 3, offsetof(Entry, fh)), nb[3], cs));
-            BHIP(nmf::i8::launch_group(rp, group_of(B, c, 4, offsetof(Entry, pa)), nb[4],
-                                       group_of(B, c, 5, offsetof(Entry, pa)), nb[5], cs));
-            if (nb[9] > 0)
-                BHIP(nmf::launch_group_exact(rp, true, group_of(B, c, 9, offsetof(Entry, hw)), nb[9], cs));
-            BHIP(nmf::launch_group_sweep(rp, true, group_of(B, c, 6, offsetof(Entry, hw)), nb[6],
-                                         group_of(B, c, 7, offsetof(Entry, fw)), nb[7], cs));
+    for (int c = 0; c < kClasses; ++c) {
+        if (B->members[c].empty()) continue;
+        if (!B->exec_one[c]) {
+            nmf_status st = capture_class(B, c, 1, &B->exec_one[c]);
+            if (st == NMF_OK && B->bp.check_every > 1)
+                st = capture_class(B, c, B->bp.check_every, &B->exec_chunk[c]);
+            if (st != NMF_OK) return st;
         }
+        int left = iters;
+        for (; B->exec_chunk[c] && left >= B->bp.check_every; left -= B->bp.check_every)
+            BHIP(hipGraphLaunch(B->exec_chunk[c], B->cs[c]));
+        for (; left > 0; --left) BHIP(hipGraphLaunch(B->exec_one[c], B->cs[c]));
+    }
     return NMF_OK;
 }
 
@@ -488,12 +543,44 @@ nmf_status finish_admissions(nmf_batch *B)
         B->arena.release(q->toff, q->tbytes);
         q->has_tmp = false;
         q->X.reset();
+        if (q->Xpin) {
+            B->pin_arena.release(q->pin_off, sizeof(float) * q->m * q->n);
+            q->Xpin = nullptr;
+        }
         std::vector<float>().swap(q->W0);
         std::vector<float>().swap(q->H0);
         B->active.push_back(q);
     }
     B->pending.clear();
     B->dirty = true;
+    return NMF_OK;
+}
+
+// Finishes the pending admissions, refreshes the tables, enqueues `chunk`
+// batch iterations of every active problem, then the set-up of newly
+// admitted problems on the batch stream beside them (uploads, slicing, e(0)).
+// *ran is false when no problem is active.
+nmf_status launch_chunk(nmf_batch *B, int chunk, bool *ran)
+{
+    *ran = false;
+    if (B->active.empty() && B->pending.empty()) {
+        nmf_status st = admit_queued(B);
+        if (st != NMF_OK) return st;
+    }
+    if (!B->pending.empty()) {
+        nmf_status st = finish_admissions(B);
+        if (st != NMF_OK) return st;
+    }
+    if (B->active.empty()) return NMF_OK;
+    if (B->dirty) {
+        nmf_status st = rebuild(B);
+        if (st != NMF_OK) return st;
+    }
+    nmf_status st = run_iterations(B, chunk);
+    if (st != NMF_OK) return st;
+    st = admit_queued(B);
+    if (st != NMF_OK) return st;
+    *ran = true;
     return NMF_OK;
 }
 
@@ -526,9 +613,17 @@ nmf_status nmf_batch_create(const nmf_batch_params *bp, nmf_batch **out)
     if (hipMalloc(&B->pool, (size_t)bp->hbm_budget) != hipSuccess)
         return cleanup(berr(NMF_E_NOMEM, "the batch arena does not fit on the device"));
     B->arena.init(B->pool, (size_t)bp->hbm_budget);
+    // Pinned staging of submitted X (1 GiB at most; without it, X is kept in
+    // pageable memory).
+    const size_t pin_bytes = std::min<size_t>((size_t)bp->hbm_budget, size_t(1) << 30);
+    if (hipHostMalloc(reinterpret_cast<void **>(&B->pin), pin_bytes) == hipSuccess)
+        B->pin_arena.init(B->pin, pin_bytes);
+    else
+        B->pin = nullptr;
     const size_t cap = (size_t)bp->max_active;
     if (hipMalloc(&B->d_entries, sizeof(Entry) * kClasses * cap) != hipSuccess ||
         hipMalloc(&B->d_prefix, sizeof(int) * kClasses * kKinds * (cap + 1)) != hipSuccess ||
+        hipMalloc(&B->d_np, sizeof(int) * kClasses) != hipSuccess ||
         hipMalloc(&B->d_states, sizeof(DevState *) * cap) != hipSuccess ||
         hipMalloc(&B->d_flags, sizeof(int32_t) * 2 * cap) != hipSuccess ||
         hipHostMalloc(&B->h_flags, sizeof(int32_t) * 2 * cap) != hipSuccess)
@@ -575,13 +670,27 @@ nmf_status nmf_batch_submit(nmf_batch *B, const nmf_matrix *X, const nmf_params 
     nmf::host::plan_product(q->pc, nmf::PK_MFMA_I8, n, q->n_pad, m, q->ldxt, kBatchTargetWG);
     if (layout(*q, nullptr) + layout_tmp(*q, nullptr) > (size_t)B->bp.hbm_budget)
         return berr(NMF_E_NOMEM, "the problem alone exceeds the batch arena");
-    q->X.reset(new (std::nothrow) float[(size_t)(m * n)]);
-    if (!q->X) return berr(NMF_E_NOMEM, "host allocation failed");
+    // X is kept until admission in the pinned pool when it fits (its upload is
+    // then an asynchronous DMA that overlaps the running iterations), else in
+    // pageable memory.
+    float *dst = nullptr;
+    size_t poff = 0;
+    if (B->pin && B->pin_arena.alloc(sizeof(float) * m * n, &poff)) {
+        q->Xpin = reinterpret_cast<float *>(B->pin_arena.base + poff);
+        q->pin_off = poff;
+        dst = q->Xpin;
+    } else {
+        q->X.reset(new (std::nothrow) float[(size_t)(m * n)]);
+        if (!q->X) return berr(NMF_E_NOMEM, "host allocation failed");
+        dst = q->X.get();
+    }
     bool nonzero = false;
-    const int64_t bad = nmf::host::copy_checked(X->dense, q->X.get(), m * n, &nonzero);
-    if (bad >= 0)
-        return berr(NMF_E_INVAL, "X has a non-finite entry at " + std::to_string(bad));
-    if (!nonzero) return berr(NMF_E_INVAL, "X is zero: the relative error is undefined");
+    const int64_t bad = nmf::host::copy_checked(X->dense, dst, m * n, &nonzero);
+    if (bad >= 0 || !nonzero) {
+        if (q->Xpin) B->pin_arena.release(poff, sizeof(float) * m * n);
+        if (bad >= 0) return berr(NMF_E_INVAL, "X has a non-finite entry at " + std::to_string(bad));
+        return berr(NMF_E_INVAL, "X is zero: the relative error is undefined");
+    }
     q->W0.assign(W0, W0 + m * r);
     q->H0.assign(H0, H0 + (int64_t)r * n);
     q->ticket = B->next_ticket++;
@@ -597,29 +706,25 @@ nmf_status nmf_batch_step(nmf_batch *B, int32_t iters, int32_t *active, int32_t 
     if (!B) return berr(NMF_E_INVAL, "batch is NULL");
     if (iters < 1) return berr(NMF_E_INVAL, "iters must be >= 1");
     BHIP(hipSetDevice(B->device));
+    // The chunk the previous call left running.
+    if (B->inflight) {
+        B->inflight = false;
+        nmf_status st = retire(B);
+        if (st != NMF_OK) return st;
+    }
     int done_iters = 0;
     while (done_iters < iters) {
-        if (B->active.empty() && B->pending.empty()) {
-            nmf_status st = admit_queued(B);
-            if (st != NMF_OK) return st;
-        }
-        if (!B->pending.empty()) {
-            nmf_status st = finish_admissions(B);
-            if (st != NMF_OK) return st;
-        }
-        if (B->active.empty()) break;
-        if (B->dirty) {
-            nmf_status st = rebuild(B);
-            if (st != NMF_OK) return st;
-        }
         const int chunk = std::min(B->bp.check_every, iters - done_iters);
-        nmf_status st = run_iterations(B, chunk);
+        bool ran = false;
+        nmf_status st = launch_chunk(B, chunk, &ran);
         if (st != NMF_OK) return st;
+        if (!ran) break;
         done_iters += chunk;
-        // The set-up of the next problems (uploads, slicing, e(0)) runs on the
-        // batch stream while the class streams run the chunk just enqueued.
-        st = admit_queued(B);
-        if (st != NMF_OK) return st;
+        if (done_iters >= iters) {
+            // Left running: the caller's work (submissions, results) overlaps it.
+            B->inflight = true;
+            break;
+        }
         st = retire(B);
         if (st != NMF_OK) return st;
     }
@@ -659,9 +764,15 @@ void nmf_batch_destroy(nmf_batch *B)
     if (B->pool) (void)hipFree(B->pool);
     if (B->d_entries) (void)hipFree(B->d_entries);
     if (B->d_prefix) (void)hipFree(B->d_prefix);
+    if (B->d_np) (void)hipFree(B->d_np);
+    for (int c = 0; c < kClasses; ++c) {
+        if (B->exec_one[c]) (void)hipGraphExecDestroy(B->exec_one[c]);
+        if (B->exec_chunk[c]) (void)hipGraphExecDestroy(B->exec_chunk[c]);
+    }
     if (B->d_states) (void)hipFree(B->d_states);
     if (B->d_flags) (void)hipFree(B->d_flags);
     if (B->h_flags) (void)hipHostFree(B->h_flags);
+    if (B->pin) (void)hipHostFree(B->pin);
     if (B->s) (void)hipStreamDestroy(B->s);
     for (int c = 0; c < kClasses; ++c)
         if (B->cs[c]) (void)hipStreamDestroy(B->cs[c]);

@@ -115,9 +115,9 @@ hipError_t launch_group_exact(int rp, bool w_side, const Group &g, int blocks, h
 }
 
 hipError_t launch_group_sweep(int rp, bool w_side, const Group &gh, int hblocks, const Group &gf,
-                              int fblocks, hipStream_t s)
+                              int fblocks, const Group &gd, int dblocks, hipStream_t s)
 {
-    NMF_RP_CALL(rp, group, w_side, gh, hblocks, gf, fblocks, s);
+    NMF_RP_CALL(rp, group, w_side, gh, hblocks, gf, fblocks, gd, dblocks, s);
     return hipGetLastError();
 }
 

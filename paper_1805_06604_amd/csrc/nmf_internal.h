@@ -199,19 +199,25 @@ struct Buffers {
 enum Counter { CNT_H = 0, CNT_W = 64, CNT_G = 128, CNT_N = 192 };
 
 // A grouped launch runs one kernel over several problems at once: problem p
-// owns blocks prefix[p] .. prefix[p + 1] - 1 of the grid and reads its
-// argument record at base + p * stride (device memory).
+// owns the work blocks prefix[p] .. prefix[p + 1] - 1 and reads its argument
+// record at base + p * stride. The tables and the problem count *np live in
+// device memory, so that a launch (and a graph of launches) stays valid while
+// the host rewrites them between batch iterations; a fixed grid walks the
+// prefix[*np] work blocks with a grid stride.
 struct Group {
     const char *base = nullptr;
     int stride = 0;
     const int *prefix = nullptr;
-    int np = 0;
+    const int *np = nullptr;
 };
 
-// Problem of block b of a grouped launch, and the block's index within it.
+// Work blocks of a grouped launch.
+__device__ inline int group_total(const Group &g) { return g.prefix[*g.np]; }
+
+// Problem of work block b of a grouped launch, and the block's index within it.
 __device__ inline int group_find(const Group &g, int b, int *local, int *count)
 {
-    int lo = 0, hi = g.np;
+    int lo = 0, hi = *g.np;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (g.prefix[mid] <= b) lo = mid;
@@ -291,6 +297,6 @@ hipError_t launch_group_exact(int rp, bool w_side, const Group &g, int blocks, h
 // into b.ginv_h / b.ginv_w (one workgroup).
 hipError_t launch_invert(int rp, bool w_side, int r, const Buffers &b, hipStream_t s);
 hipError_t launch_group_sweep(int rp, bool w_side, const Group &gh, int hblocks, const Group &gf,
-                              int fblocks, hipStream_t s);
+                              int fblocks, const Group &gd, int dblocks, hipStream_t s);
 
 }  // namespace nmf

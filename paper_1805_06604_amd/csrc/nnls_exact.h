@@ -380,9 +380,13 @@ __global__ __launch_bounds__(kThreads) void invert_kernel(HalsArgs a)
 template <int RP, int MODE>
 __global__ __launch_bounds__(kThreads, 2) void exact_group_kernel(Group g)
 {
-    int lb, cnt;
-    const int p = group_find(g, blockIdx.x, &lb, &cnt);
-    exact_body<RP, MODE>(*reinterpret_cast<const HalsArgs *>(g.base + (size_t)p * g.stride), lb);
+    const int total = group_total(g);
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        int lb, cnt;
+        const int p = group_find(g, b, &lb, &cnt);
+        exact_body<RP, MODE>(*reinterpret_cast<const HalsArgs *>(g.base + (size_t)p * g.stride), lb);
+        __syncthreads();
+    }
 }
 
 }  // namespace sweep

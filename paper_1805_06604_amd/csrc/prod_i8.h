@@ -272,20 +272,34 @@ __global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_kernel(ProdArgs a)
 }
 
 // Grouped forms (one launch over several problems of one padded rank).
+// Each workgroup takes the work blocks blockIdx.x, blockIdx.x + gridDim.x,
+// ... in turn, with a barrier between two blocks (LDS reuse).
 template <int RP>
 __global__ __launch_bounds__(256) void slice_factor_group_kernel(Group g)
 {
-    int lb, cnt;
-    const int p = group_find(g, blockIdx.x, &lb, &cnt);
-    slice_body<RP>(*reinterpret_cast<const ProdArgs *>(g.base + (size_t)p * g.stride), lb);
+    const int total = group_total(g);
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        int lb, cnt;
+        const int p = group_find(g, b, &lb, &cnt);
+        slice_body<RP>(*reinterpret_cast<const ProdArgs *>(g.base + (size_t)p * g.stride), lb);
+        __syncthreads();
+    }
 }
 
 template <int RP>
 __global__ __launch_bounds__(kWaves * 64, 1) void prod_i8_group_kernel(Group g)
 {
-    int lb, cnt;
-    const int p = group_find(g, blockIdx.x, &lb, &cnt);
-    prod_body<RP>(*reinterpret_cast<const ProdArgs *>(g.base + (size_t)p * g.stride), lb);
+    const int total = group_total(g);
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        int lb, cnt;
+        const int p = group_find(g, b, &lb, &cnt);
+        prod_body<RP>(*reinterpret_cast<const ProdArgs *>(g.base + (size_t)p * g.stride), lb);
+        // The body ends with loads past its last tile still in flight (into
+        // registers and, by direct loads, into the LDS ring): all of them
+        // land before the next block reuses the ring.
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
 }
 
 // Blocks of the two kernels of one product.

@@ -548,60 +548,36 @@ struct FinArgs {
 constexpr int kFinOut = 64;
 constexpr int kFinSplit = 4;
 
+// Destination of output e of the records: the Gram entry (and the inverse
+// diagonal beside a diagonal entry), a column maximum, or one of the scalars
+// <x, c> and the beta* numerator and denominator.
 template <int RP, int MODE>
-__device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
+__device__ __forceinline__ void fin_store(const FinArgs &a, const int *slot, int e, double s)
 {
     constexpr int NG = ModeInfo<MODE>::ngram;
     constexpr int GL = RP * RP + RP;
-    constexpr int LREC = rec_len<RP>(NG);
-    __shared__ double sh[kFinSplit][kFinOut];
-    __shared__ double shd[4];
-    __shared__ int s_last;
-    DevState *st = a.st;
-    int slot[NG];
-    if constexpr (MODE == SWEEP_H || MODE == SWEEP_W) {
-        if (st->done) return;
-    }
-    if constexpr (MODE == SWEEP_W) {
-        slot[0] = st->w_n;
-        slot[NG - 1] = st->w_yn;
-    } else {
-        slot[0] = 0;
-    }
-    const int o = threadIdx.x & (kFinOut - 1), j = threadIdx.x / kFinOut;
-    const int e = bid * kFinOut + o;
-    const bool is_max = e < NG * GL && (e % GL) >= RP * RP;
-    double v = 0.0;
-    if (e < LREC) {
-        const double *src = a.part + e;
-#pragma unroll 8
-        for (int b = j; b < a.nblk; b += kFinSplit) {
-            const double x = src[(size_t)b * LREC];
-            v = is_max ? fmax(v, x) : v + x;
+    if (e < NG * GL) {
+        const int gi = e / GL, w = e % GL;
+        double *Gd = a.gram + slot[gi] * a.gram_slot_stride;
+        if (w < RP * RP) {
+            Gd[w] = s;
+            const int k = w / RP, l = w % RP;
+            if (k == l) Gd[RP * RP + k] = (k < a.r && s > 0.0) ? 1.0 / s : 0.0;
+        } else {
+            Gd[RP * RP + RP + (w - RP * RP)] = s;
         }
+    } else if (ModeInfo<MODE>::s1) {
+        a.scratch[e - NG * GL] = s;        // <x, c>, beta* numerator, denominator
     }
-    sh[j][o] = v;
-    __syncthreads();
-    if (j == 0 && e < LREC) {          // wave 0
-        double s = sh[0][o];
-#pragma unroll
-        for (int q = 1; q < kFinSplit; ++q) s = is_max ? fmax(s, sh[q][o]) : s + sh[q][o];
-        if (e < NG * GL) {
-            const int gi = e / GL, w = e % GL;
-            double *Gd = a.gram + slot[gi] * a.gram_slot_stride;
-            if (w < RP * RP) {
-                Gd[w] = s;
-                const int k = w / RP, l = w % RP;
-                if (k == l) Gd[RP * RP + k] = (k < a.r && s > 0.0) ? 1.0 / s : 0.0;
-            } else {
-                Gd[RP * RP + RP + (w - RP * RP)] = s;
-            }
-        } else if (ModeInfo<MODE>::s1) {
-            a.scratch[e - NG * GL] = s;        // <x, c>, beta* numerator, denominator
-        }
-    }
-    if (!last_block(a.counter, &s_last, nblk)) return;
+}
+
+// After every output is stored and visible to the calling workgroup: s2,
+// then e(k) and the decision (W sweep), or e(0) (W set-up).
+template <int RP, int MODE>
+__device__ __forceinline__ void fin_decide(const FinArgs &a, const int *slot, double *shd)
+{
     if constexpr (ModeInfo<MODE>::s1) {
+        DevState *st = a.st;
         const double *Gn = a.gram + slot[0] * a.gram_slot_stride;
         double s2 = 0.0;
         for (int q = threadIdx.x; q < RP * RP; q += 256) s2 = fma(Gn[q], a.GH[q], s2);
@@ -627,7 +603,108 @@ __device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
             }
         }
     }
+}
+
+template <int RP, int MODE>
+__device__ __forceinline__ void fin_slots(const DevState *st, int *slot)
+{
+    constexpr int NG = ModeInfo<MODE>::ngram;
+    if constexpr (MODE == SWEEP_W) {
+        slot[0] = st->w_n;
+        slot[NG - 1] = st->w_yn;
+    } else {
+        slot[0] = 0;
+    }
+}
+
+template <int RP, int MODE>
+__device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
+{
+    constexpr int NG = ModeInfo<MODE>::ngram;
+    constexpr int GL = RP * RP + RP;
+    constexpr int LREC = rec_len<RP>(NG);
+    __shared__ double sh[kFinSplit][kFinOut];
+    __shared__ double shd[4];
+    __shared__ int s_last;
+    DevState *st = a.st;
+    int slot[NG];
+    if constexpr (MODE == SWEEP_H || MODE == SWEEP_W) {
+        if (st->done) return;
+    }
+    fin_slots<RP, MODE>(st, slot);
+    const int o = threadIdx.x & (kFinOut - 1), j = threadIdx.x / kFinOut;
+    const int e = bid * kFinOut + o;
+    const bool is_max = e < NG * GL && (e % GL) >= RP * RP;
+    double v = 0.0;
+    if (e < LREC) {
+        const double *src = a.part + e;
+#pragma unroll 8
+        for (int b = j; b < a.nblk; b += kFinSplit) {
+            const double x = src[(size_t)b * LREC];
+            v = is_max ? fmax(v, x) : v + x;
+        }
+    }
+    sh[j][o] = v;
+    __syncthreads();
+    if (j == 0 && e < LREC) {          // wave 0
+        double s = sh[0][o];
+#pragma unroll
+        for (int q = 1; q < kFinSplit; ++q) s = is_max ? fmax(s, sh[q][o]) : s + sh[q][o];
+        fin_store<RP, MODE>(a, slot, e, s);
+    }
+    if (!last_block(a.counter, &s_last, nblk)) return;
+    fin_decide<RP, MODE>(a, slot, shd);
     if (threadIdx.x == 0) reset_counter(a.counter);
+}
+
+// The same two steps as two launches, for batched problems: finish_sum_body
+// is the summing part of finish_body (kFinOut outputs per work block, the
+// same order of records), with no completion counter and no cross-workgroup
+// fence; finish_decide_body, one work block per problem in the next launch
+// (the launch boundary makes the sums visible), is its decision part.
+template <int RP, int MODE>
+__device__ __forceinline__ void finish_sum_body(const FinArgs &a, int bid)
+{
+    constexpr int NG = ModeInfo<MODE>::ngram;
+    constexpr int GL = RP * RP + RP;
+    constexpr int LREC = rec_len<RP>(NG);
+    __shared__ double sh[kFinSplit][kFinOut];
+    DevState *st = a.st;
+    int slot[NG];
+    if (st->done) return;
+    fin_slots<RP, MODE>(st, slot);
+    const int o = threadIdx.x & (kFinOut - 1), j = threadIdx.x / kFinOut;
+    const int e = bid * kFinOut + o;
+    const bool is_max = e < NG * GL && (e % GL) >= RP * RP;
+    double v = 0.0;
+    if (e < LREC) {
+        const double *src = a.part + e;
+#pragma unroll 8
+        for (int b = j; b < a.nblk; b += kFinSplit) {
+            const double x = src[(size_t)b * LREC];
+            v = is_max ? fmax(v, x) : v + x;
+        }
+    }
+    sh[j][o] = v;
+    __syncthreads();
+    if (j == 0 && e < LREC) {
+        double s = sh[0][o];
+#pragma unroll
+        for (int q = 1; q < kFinSplit; ++q) s = is_max ? fmax(s, sh[q][o]) : s + sh[q][o];
+        fin_store<RP, MODE>(a, slot, e, s);
+    }
+}
+
+template <int RP, int MODE>
+__device__ __forceinline__ void finish_decide_body(const FinArgs &a)
+{
+    constexpr int NG = ModeInfo<MODE>::ngram;
+    __shared__ double shd[4];
+    DevState *st = a.st;
+    int slot[NG];
+    if (st->done) return;
+    fin_slots<RP, MODE>(st, slot);
+    fin_decide<RP, MODE>(a, slot, shd);
 }
 
 // Decision of the adaptive inner loop after one sweep (one workgroup): the
@@ -679,21 +756,44 @@ __global__ __launch_bounds__(256) void finish_kernel(FinArgs a)
 }
 
 // Grouped forms: one launch over several problems of the same padded rank
-// (argument records and block ranges in g).
+// (argument records and block ranges in g), each workgroup taking the work
+// blocks blockIdx.x, blockIdx.x + gridDim.x, ... in turn; the barrier between
+// two blocks keeps one block's LDS reads ahead of the next block's writes.
 template <int RP, int MODE>
 __global__ __launch_bounds__(kThreads, 1) void hals_group_kernel(Group g)
 {
-    int lb, cnt;
-    const int p = group_find(g, blockIdx.x, &lb, &cnt);
-    hals_body<RP, MODE>(*reinterpret_cast<const HalsArgs *>(g.base + (size_t)p * g.stride), lb);
+    const int total = group_total(g);
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        int lb, cnt;
+        const int p = group_find(g, b, &lb, &cnt);
+        hals_body<RP, MODE>(*reinterpret_cast<const HalsArgs *>(g.base + (size_t)p * g.stride), lb);
+        __syncthreads();
+    }
 }
 
 template <int RP, int MODE>
 __global__ __launch_bounds__(256) void finish_group_kernel(Group g)
 {
-    int lb, cnt;
-    const int p = group_find(g, blockIdx.x, &lb, &cnt);
-    finish_body<RP, MODE>(*reinterpret_cast<const FinArgs *>(g.base + (size_t)p * g.stride), lb, cnt);
+    const int total = group_total(g);
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        int lb, cnt;
+        const int p = group_find(g, b, &lb, &cnt);
+        finish_sum_body<RP, MODE>(*reinterpret_cast<const FinArgs *>(g.base + (size_t)p * g.stride), lb);
+        __syncthreads();
+    }
+}
+
+// One work block per problem.
+template <int RP, int MODE>
+__global__ __launch_bounds__(256) void decide_group_kernel(Group g)
+{
+    const int total = group_total(g);
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        int lb, cnt;
+        const int p = group_find(g, b, &lb, &cnt);
+        finish_decide_body<RP, MODE>(*reinterpret_cast<const FinArgs *>(g.base + (size_t)p * g.stride));
+        __syncthreads();
+    }
 }
 
 // Exact NNLS solve of every factor row (E-ANLS), defined in nnls_exact.h:
@@ -783,19 +883,21 @@ struct Launch {
         finish_kernel<RP, MODE><<<fin_blocks(RP, NG), 256, 0, s>>>(f);
     }
     // Grouped half-iteration: the sweep kernel over group gh, then the
-    // finish kernel over group gf.
+    // summing finish kernel over group gf (and, W side, the decision).
     // Grouped exact NNLS solves (the problems of the group that use them).
     static void exact_group(bool w_side, const Group &g, int blocks, hipStream_t s)
     {
         if (w_side) exact_group_kernel<RP, SWEEP_W><<<blocks, kThreads, 0, s>>>(g);
         else exact_group_kernel<RP, SWEEP_H><<<blocks, kThreads, 0, s>>>(g);
     }
+    // The W side adds the decision launch over group gd.
     static void group(bool w_side, const Group &gh, int hblocks, const Group &gf, int fblocks,
-                      hipStream_t s)
+                      const Group &gd, int dblocks, hipStream_t s)
     {
         if (w_side) {
             hals_group_kernel<RP, SWEEP_W><<<hblocks, kThreads, 0, s>>>(gh);
             finish_group_kernel<RP, SWEEP_W><<<fblocks, 256, 0, s>>>(gf);
+            decide_group_kernel<RP, SWEEP_W><<<dblocks, 256, 0, s>>>(gd);
         } else {
             hals_group_kernel<RP, SWEEP_H><<<hblocks, kThreads, 0, s>>>(gh);
             finish_group_kernel<RP, SWEEP_H><<<fblocks, 256, 0, s>>>(gf);

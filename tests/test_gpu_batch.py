@@ -104,3 +104,24 @@ def test_batch_rejects_the_adaptive_inner_rule():
         with pytest.raises(P.NMFError) as e:
             B.submit(p.X, p.r, p.W0, p.H0, inner_rule=P.Inner.ADAPTIVE)
     assert e.value.status == P.Status.E_UNSUPPORTED
+
+
+def test_each_problem_is_the_same_alone_and_in_the_mix():
+    """Continuous batching does not change a problem's result: each problem
+    run alone in a batch equals the same problem run among the others bit for
+    bit (its work blocks, K-chunks and reductions do not depend on the other
+    problems), and equals the single-problem solve (whose product kernels
+    split K differently) within the parity tolerances on the trace, W and H."""
+    from parity import rel_fro
+    probs = _problems()
+    mix = _run_batch(probs, 1 << 30, 30, check_every=5)
+    for p, g in zip(probs, mix):
+        print(f"problem m={p.m} n={p.n} r={p.r}", flush=True)
+        alone = _run_batch([p], 1 << 30, 30, check_every=5)[0]
+        assert np.array_equal(alone.trace, g.trace)
+        assert np.array_equal(alone.W, g.W) and np.array_equal(alone.H, g.H)
+        with P.Solver(p.X, p.r, max_iter=30, hp=3, prod=P.Prod.MFMA_EXACT, **ALG) as s:
+            single = s.solve(p.W0, p.H0)
+        assert np.array_equal(single.accepted, g.accepted)
+        np.testing.assert_allclose(g.trace, single.trace, rtol=1e-5)
+        assert rel_fro(g.W, single.W) < 1e-4 and rel_fro(g.H, single.H) < 1e-4
