@@ -362,7 +362,12 @@ nmf_status nmf_batch_result(nmf_batch *b, int64_t ticket, float *W, float *H, do
                             int32_t trace_cap, int32_t *n_iter, uint8_t *accepted,
                             double *beta);
 
-/* Frees the arena and every pending problem. NULL is allowed. */
+/* Frees the arena and every pending problem. NULL is allowed. Waits for the
+ * device work of the batch first.
+ * Threads: nmf_batch_submit and nmf_batch_result may be called from other
+ * threads while nmf_batch_step runs (a serving loop stepping the batch while
+ * requests are submitted); calls of nmf_batch_step must not overlap one
+ * another, and nmf_batch_destroy must not overlap any call. */
 void nmf_batch_destroy(nmf_batch *b);
 
 /* Frees every host and device resource of ctx. NULL is allowed. */

@@ -24,6 +24,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -208,6 +209,10 @@ struct nmf_batch {
     std::map<int64_t, std::unique_ptr<Prob>> all;
     int64_t next_ticket = 1;
     int32_t retired_unread = 0;
+    // Guards what submissions and results share with the stepping thread:
+    // queue, all, next_ticket, retired_unread, pin_arena and the retired
+    // flags and results of the problems.
+    std::mutex mu;
     // grouped-launch tables (device), rebuilt when the active set changes
     bool dirty = true;
     Entry *d_entries = nullptr;          // kClasses x max_active
@@ -507,6 +512,7 @@ nmf_status retire(nmf_batch *B)
         }
         BHIP(hipStreamSynchronize(B->s));
         B->arena.release(q->off, q->bytes);
+        std::lock_guard<std::mutex> lk(B->mu);
         q->retired = true;
         ++B->retired_unread;
         B->dirty = true;
@@ -519,6 +525,7 @@ nmf_status retire(nmf_batch *B)
 // allow, enqueueing their set-up on the batch stream (see admit).
 nmf_status admit_queued(nmf_batch *B)
 {
+    std::lock_guard<std::mutex> lk(B->mu);
     while (!B->queue.empty() &&
            (int)(B->active.size() + B->pending.size()) < B->bp.max_active) {
         Prob *q = B->queue.front();
@@ -544,6 +551,7 @@ nmf_status finish_admissions(nmf_batch *B)
         q->has_tmp = false;
         q->X.reset();
         if (q->Xpin) {
+            std::lock_guard<std::mutex> lk(B->mu);
             B->pin_arena.release(q->pin_off, sizeof(float) * q->m * q->n);
             q->Xpin = nullptr;
         }
@@ -675,8 +683,13 @@ nmf_status nmf_batch_submit(nmf_batch *B, const nmf_matrix *X, const nmf_params 
     // pageable memory.
     float *dst = nullptr;
     size_t poff = 0;
-    if (B->pin && B->pin_arena.alloc(sizeof(float) * m * n, &poff)) {
-        q->Xpin = reinterpret_cast<float *>(B->pin_arena.base + poff);
+    bool pinned = false;
+    if (B->pin) {
+        std::lock_guard<std::mutex> lk(B->mu);
+        pinned = B->pin_arena.alloc(sizeof(float) * m * n, &poff);
+    }
+    if (pinned) {
+        q->Xpin = reinterpret_cast<float *>(B->pin + poff);
         q->pin_off = poff;
         dst = q->Xpin;
     } else {
@@ -687,12 +700,16 @@ nmf_status nmf_batch_submit(nmf_batch *B, const nmf_matrix *X, const nmf_params 
     bool nonzero = false;
     const int64_t bad = nmf::host::copy_checked(X->dense, dst, m * n, &nonzero);
     if (bad >= 0 || !nonzero) {
-        if (q->Xpin) B->pin_arena.release(poff, sizeof(float) * m * n);
+        if (q->Xpin) {
+            std::lock_guard<std::mutex> lk(B->mu);
+            B->pin_arena.release(poff, sizeof(float) * m * n);
+        }
         if (bad >= 0) return berr(NMF_E_INVAL, "X has a non-finite entry at " + std::to_string(bad));
         return berr(NMF_E_INVAL, "X is zero: the relative error is undefined");
     }
     q->W0.assign(W0, W0 + m * r);
     q->H0.assign(H0, H0 + (int64_t)r * n);
+    std::lock_guard<std::mutex> lk(B->mu);
     q->ticket = B->next_ticket++;
     *ticket = q->ticket;
     B->queue.push_back(q.get());
@@ -728,6 +745,7 @@ nmf_status nmf_batch_step(nmf_batch *B, int32_t iters, int32_t *active, int32_t 
         st = retire(B);
         if (st != NMF_OK) return st;
     }
+    std::lock_guard<std::mutex> lk(B->mu);
     if (active) *active = (int32_t)(B->active.size() + B->pending.size());
     if (queued) *queued = (int32_t)B->queue.size();
     if (retired) *retired = B->retired_unread;
@@ -738,6 +756,7 @@ nmf_status nmf_batch_result(nmf_batch *B, int64_t ticket, float *W, float *H, do
                             int32_t trace_cap, int32_t *n_iter, uint8_t *accepted, double *beta)
 {
     if (!B) return berr(NMF_E_INVAL, "batch is NULL");
+    std::lock_guard<std::mutex> lk(B->mu);
     auto it = B->all.find(ticket);
     if (it == B->all.end()) return berr(NMF_E_INVAL, "unknown ticket");
     Prob &q = *it->second;

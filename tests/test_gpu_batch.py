@@ -125,3 +125,43 @@ def test_each_problem_is_the_same_alone_and_in_the_mix():
         assert np.array_equal(single.accepted, g.accepted)
         np.testing.assert_allclose(g.trace, single.trace, rtol=1e-5)
         assert rel_fro(g.W, single.W) < 1e-4 and rel_fro(g.H, single.H) < 1e-4
+
+
+def test_submissions_from_another_thread_while_stepping():
+    """A serving loop: one thread steps the batch and collects results while
+    another submits problems over time. Every result equals the same problem
+    run alone, bit for bit."""
+    import threading
+    import time
+    probs = _problems() * 3
+    got = {}
+    with P.Batch(1 << 30, max_active=64, check_every=5) as B:
+        tickets = []
+        done = threading.Event()
+
+        def step():
+            while not done.is_set() or len(got) < len(probs):
+                B.step(5)
+                for i, t in enumerate(list(tickets)):
+                    if i not in got:
+                        g = B.result(t)
+                        if g is not None:
+                            got[i] = g
+                if done.is_set() and len(got) == len(tickets):
+                    break
+                time.sleep(0.0005)
+
+        th = threading.Thread(target=step)
+        th.start()
+        for p in probs:
+            tickets.append(B.submit(p.X, p.r, p.W0, p.H0, max_iter=25, hp=3, **ALG))
+            time.sleep(0.002)
+        done.set()
+        th.join(timeout=120)
+        assert not th.is_alive()
+    assert len(got) == len(probs)
+    for i, p in enumerate(probs[:len(_problems())]):
+        alone = _run_batch([p], 1 << 30, 25, check_every=5)[0]
+        for j in (i, i + len(_problems()), i + 2 * len(_problems())):
+            assert np.array_equal(got[j].trace, alone.trace)
+            assert np.array_equal(got[j].W, alone.W) and np.array_equal(got[j].H, alone.H)
