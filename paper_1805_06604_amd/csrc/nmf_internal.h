@@ -137,7 +137,8 @@ struct ProdArgs {
     int64_t slot_stride;
     int sel;                // FactorSel
     const DevState *st;
-    double *Y;              // nsplit x rows_pad x RP partial sums (FP64)
+    double *Y;              // nsplit x rows_pad x RP partial sums (FP64; FP32 for the
+                            // 16-bit X product, whose sums within a K-chunk are FP32)
     int64_t kchunk;         // K per split, multiple of 64
     int nsplit;
     // Exact-integer kernel only: per-row scale exponents of Z, and the Gram
@@ -172,6 +173,7 @@ struct Buffers {
     double *A = nullptr;     // nsplit_a x m_pad x RP : partials of X H_w^T
     double *Ct = nullptr;    // nsplit_c x n_pad x RP : partials of X^T W_y
     int nsplit_a = 1, nsplit_c = 1;
+    bool lin_f32 = false;    // A and Ct hold FP32 partials (the 16-bit X product)
     int64_t m_pad = 0, n_pad = 0;
     double *part_g = nullptr;// per-workgroup records of the sweep kernels
     double *part_d = nullptr;// FP64 scratch: reduction partials, the summed <W, A>

@@ -160,9 +160,7 @@ __device__ __forceinline__ void exact_body(const HalsArgs &a, int bid)
         const bool valid = row < a.rows && k < RP;
         double c = 0.0, w = 0.0;
         if (valid) {
-            const double *p = a.lin + row * RP + k;
-            c = p[0];
-            for (int sp = 1; sp < a.nsplit; ++sp) c += p[sp * a.split_stride];
+            c = lin_sum(a, row * RP + k);
             w = (double)xsrc[row * RP + k];
         }
         const bool pos = valid && k < a.r && s_g[kk * RP + kk] > 0.0;

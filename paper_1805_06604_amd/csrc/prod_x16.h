@@ -7,7 +7,8 @@
 // one part; FP16 X is split on the fly into two (exact). The part pairs of
 // relative weight >= 2^-8 are kept (x0 f0, x0 f1, and x1 f0 for FP16) and
 // accumulated in FP32 on v_mfma_f32_16x16x32_bf16 within the K-chunk; the
-// K-chunk partials are written in FP64 and summed by the sweep kernels.
+// K-chunk partials are written in FP32 and summed in FP64 by the sweep
+// kernels.
 //
 // Z layout (fragment order). The 16-bit copy of Z (X or the resident X^T) is
 // stored per 16-row block and 64-column tile as 2 k-steps x 64 lanes x 16
@@ -243,15 +244,17 @@ __device__ __forceinline__ void prod_body(const ProdArgs &args, int bid)
         __builtin_amdgcn_s_waitcnt(0x0070);            // vmcnt(0): no load outlives the loop
     }
 
-    // D layout: lane holds column lr of each block, rows 4g..4g+3.
-    double *Y = a.Y + (size_t)kc * a.rows_pad * RP;
+    // D layout: lane holds column lr of each block, rows 4g..4g+3. The
+    // K-chunk's FP32 sums are stored as they are (FP32 partials; the sweep
+    // kernels add them in FP64).
+    float *Y = reinterpret_cast<float *>(a.Y) + (size_t)kc * a.rows_pad * RP;
 #pragma unroll
     for (int b = 0; b < kBPW; ++b)
 #pragma unroll
         for (int c = 0; c < NCB; ++c)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                Y[(row0 + 16 * b + 4 * g + i) * RP + c * 16 + lr] = (double)acc[b][c][i];
+                Y[(row0 + 16 * b + 4 * g + i) * RP + c * 16 + lr] = acc[b][c][i];
 }
 
 template <int RP>

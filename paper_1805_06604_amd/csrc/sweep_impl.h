@@ -159,6 +159,7 @@ struct HalsArgs {
     int64_t rows;          // factor rows (m for W, n for H^T)
     int r, K;
     const double *lin;     // nsplit x (rows_pad x RP) partials of the linear term
+    const float *lin32;    // the same in FP32 (16-bit X products), used when non-null
     int nsplit;
     int64_t split_stride;
     float *fac;            // factor slots, rows x RP each
@@ -181,6 +182,22 @@ struct HalsArgs {
     // computed beforehand, or null for an inversion in every workgroup.
     double *ginv;
 };
+
+// Linear term of one coordinate: its K-chunk partials summed in FP64 in
+// split order.
+__device__ __forceinline__ double lin_sum(const HalsArgs &a, int64_t off)
+{
+    if (a.lin32) {
+        const float *p = a.lin32 + off;
+        double c = p[0];
+        for (int sp = 1; sp < a.nsplit; ++sp) c += (double)p[sp * a.split_stride];
+        return c;
+    }
+    const double *p = a.lin + off;
+    double c = p[0];
+    for (int sp = 1; sp < a.nsplit; ++sp) c += p[sp * a.split_stride];
+    return c;
+}
 
 // SETUP_H / SETUP_W: Gram (and for W, <W0, A>) of slot 0.
 // SWEEP_H (a3 + a4): H_n from H_y by K sweeps with C^T = X^T W_y and
@@ -241,11 +258,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
             xd[b][v] = ok ? (x64 ? x64[off] : (double)xsrc[off]) : 0.0;
             double c = 0.0;
             if constexpr (MI::lin) {
-                if (ok) {
-                    const double *p = a.lin + row * RP + 16 * b + lr;
-                    c = p[0];
-                    for (int sp = 1; sp < a.nsplit; ++sp) c += p[sp * a.split_stride];
-                }
+                if (ok) c = lin_sum(a, row * RP + 16 * b + lr);
             }
             cd[b][v] = c;
         }
@@ -817,6 +830,7 @@ inline HalsArgs hals_args(int rp, int64_t rows, int r, int K, const Buffers &b, 
     h.K = K;
     h.fac = w_side ? b.Wf : b.Hf;
     h.slot_stride = rows * rp;
+    if (b.lin_f32) h.lin32 = reinterpret_cast<const float *>(w_side ? b.A : b.Ct);
     if (w_side) {
         h.lin = b.A;
         h.nsplit = b.nsplit_a;
