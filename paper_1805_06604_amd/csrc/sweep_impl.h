@@ -247,20 +247,49 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
     const double *x64 = (MI::sweeps && a.src_mode == 2) ? a.x64 : nullptr;
 
     // x and c in D layout: rows 4v+g of the wave's tile, coordinate 16b+lr.
+    // The loop over the K-chunk partials of c runs outside the unrolled tile
+    // loops, so that all loads of one partial are in flight together (the
+    // sum per entry is still p0 + p1 + ... in split order).
+    // Rows past the factor's end read the last row (in bounds, every load
+    // unconditional so that they are all in flight together) and count as 0.
     double xd[NB][4], cd[NB][4];
+    bool okv[4];
+    int64_t rowc[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int64_t row = row0 + 4 * v + g;
-        const bool ok = row < a.rows;
+        okv[v] = row < a.rows;
+        rowc[v] = okv[v] ? row : a.rows - 1;
+    }
+    auto load_x = [&](auto ld) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int64_t off = row * RP + 16 * b + lr;
-            xd[b][v] = ok ? (x64 ? x64[off] : (double)xsrc[off]) : 0.0;
-            double c = 0.0;
-            if constexpr (MI::lin) {
-                if (ok) c = lin_sum(a, row * RP + 16 * b + lr);
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const double x = ld(rowc[v] * RP + 16 * b + lr);
+                xd[b][v] = okv[v] ? x : 0.0;
+                cd[b][v] = 0.0;
             }
-            cd[b][v] = c;
+    };
+    if (x64) load_x([&](int64_t off) { return x64[off]; });
+    else load_x([&](int64_t off) { return (double)xsrc[off]; });
+    if constexpr (MI::lin) {
+        auto add_split = [&](auto load, int sp) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const double c = load(sp * a.split_stride + rowc[v] * RP + 16 * b + lr);
+                    const double nv = (sp == 0) ? c : cd[b][v] + c;
+                    cd[b][v] = okv[v] ? nv : 0.0;
+                }
+        };
+        if (a.lin32) {
+            auto ld = [&](int64_t off) { return (double)a.lin32[off]; };
+            for (int sp = 0; sp < a.nsplit; ++sp) add_split(ld, sp);
+        } else {
+            auto ld = [&](int64_t off) { return a.lin[off]; };
+            for (int sp = 0; sp < a.nsplit; ++sp) add_split(ld, sp);
         }
     }
 
@@ -273,27 +302,47 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
         // corrections of the scaled numerators.
         // B operands in LDS (shared by the four waves, read right before each
         // MFMA): s_gb[s][b][lane] = -G(4s+g, 16b+lr).
-        double inv[NB];
-        for (int e = tid; e < NS * NB * 64; e += kThreads) {
-            const int sb = e >> 6, ln = e & 63;
+        // (All global loads of the staging first, then the LDS stores.)
+        constexpr int NGB = NS * NB * 64 / kThreads, NTR = NB * 256 / kThreads;
+        static_assert(NGB * kThreads == NS * NB * 64 && NTR * kThreads == NB * 256, "staging split");
+        double inv[NB], gtmp[NGB], ttmp[NTR];
+#pragma unroll
+        for (int i = 0; i < NGB; ++i) {
+            const int e = tid + i * kThreads, sb = e >> 6, ln = e & 63;
             const int ss = sb / NB, bb = sb % NB;
-            s_gb[ss][bb][ln] = -G[(4 * ss + (ln >> 4)) * RP + 16 * bb + (ln & 15)];
+            gtmp[i] = -G[(4 * ss + (ln >> 4)) * RP + 16 * bb + (ln & 15)];
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) inv[b] = G[RP * RP + 16 * b + lr];
-        for (int e = tid; e < NB * 256; e += kThreads) {
-            const int b = e >> 8, q = (e >> 4) & 15, l = e & 15;
-            s_tri[b][q][l] = (l > q) ? G[(16 * b + l) * RP + 16 * b + q] * G[RP * RP + 16 * b + l] : 0.0;
+#pragma unroll
+        for (int i = 0; i < NTR; ++i) {
+            const int e = tid + i * kThreads, b = e >> 8, q = (e >> 4) & 15, l = e & 15;
+            ttmp[i] = (l > q) ? G[(16 * b + l) * RP + 16 * b + q] * G[RP * RP + 16 * b + l] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < NGB; ++i) {
+            const int e = tid + i * kThreads, sb = e >> 6, ln = e & 63;
+            s_gb[sb / NB][sb % NB][ln] = gtmp[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NTR; ++i) {
+            const int e = tid + i * kThreads;
+            s_tri[e >> 8][(e >> 4) & 15][e & 15] = ttmp[i];
         }
         // x in A layout: row lr, coordinate 4s+g.
         {
             const int64_t row = row0 + lr;
             const bool ok = row < a.rows;
+            const int64_t rc = ok ? row : a.rows - 1;
+            auto load_xa = [&](auto ld) {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int64_t off = row * RP + 4 * s + g;
-                xa[s] = ok ? (x64 ? x64[off] : (double)xsrc[off]) : 0.0;
-            }
+                for (int s = 0; s < NS; ++s) {
+                    const double x = ld(rc * RP + 4 * s + g);
+                    xa[s] = ok ? x : 0.0;
+                }
+            };
+            if (x64) load_xa([&](int64_t off) { return x64[off]; });
+            else load_xa([&](int64_t off) { return (double)xsrc[off]; });
         }
         __syncthreads();
         double *xs = s_buf + wave * 16 * XLD;
@@ -401,6 +450,16 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
     double gw[NG][NB][4];
     double dw[NB][4];          // W_n - W (beta* diagnostic)
     double s1 = 0.0;
+    // The accepted rows first, all loads in flight together (the accepted
+    // slot is never written by this kernel).
+    float prv[NB][4];
+    if constexpr (MI::sweeps) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                prv[b][v] = a.fac[acc_slot * a.slot_stride + rowc[v] * RP + 16 * b + lr];
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int64_t row = row0 + 4 * v + g;
@@ -414,7 +473,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                 dw[b][v] = 0.0;
                 if (ok) {
                     a.fac[dst_n * a.slot_stride + off] = xn;
-                    const float prev = a.fac[acc_slot * a.slot_stride + off];
+                    const float prev = prv[b][v];
                     dw[b][v] = xd[b][v] - (double)prev;
                     double y = fma(beta, (double)xn - (double)prev, (double)xn);
                     if (MODE == SWEEP_H && hp == 3) y = fmax(y, 0.0);
