@@ -57,15 +57,30 @@ __host__ __device__ constexpr int rec_len(int ngram) { return ngram * (RP * RP +
 // Solver flags read on the device (the NMF_FLAG_* values of the C ABI).
 constexpr int kFlagBetaStar = 4;
 
-// Value of lane Q of this lane's 16-lane row.
+// One coordinate step on the four rows a lane holds. Every lane forms the
+// change its own coordinate would take, d = max(t, -x); the change of lane Q
+// of the 16-lane row is then taken into t, t -= gq * d(lane Q). The broadcast
+// rides on the multiply-add as its DPP source (v_fmac_f64 with row_newbcast:Q
+// on the negated src0), which the compiler does not form by itself: 8
+// instructions per step instead of 12 with a separate v_mov_b64_dpp per row.
+// Rounding is that of fma(-gq, d, t). Each DPP source is written three
+// instructions before it is read, more than the two wait states a DPP read
+// of a VALU result needs; no memory is touched.
 template <int Q>
-__device__ __forceinline__ double row_bcast(double v)
+__device__ __forceinline__ void step4(double &t0, double &t1, double &t2, double &t3, double x0,
+                                      double x1, double x2, double x3, double gq)
 {
-    // Every lane is written, so the "old" operand is the source itself (no
-    // extra register initialisation).
-    const long x = __builtin_bit_cast(long, v);
-    const long b = __builtin_amdgcn_update_dpp(x, x, 0x150 + Q, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, b);
+    double d0, d1, d2, d3;
+    asm("v_max_f64 %0, %4, -%8\n\t"
+        "v_max_f64 %1, %5, -%9\n\t"
+        "v_max_f64 %2, %6, -%10\n\t"
+        "v_max_f64 %3, %7, -%11\n\t"
+        "v_fmac_f64_dpp %4, -%0, %12 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %5, -%1, %12 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %6, -%2, %12 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %7, -%3, %12 row_newbcast:%13 row_mask:0xf bank_mask:0xf"
+        : "=&v"(d0), "=&v"(d1), "=&v"(d2), "=&v"(d3), "+v"(t0), "+v"(t1), "+v"(t2), "+v"(t3)
+        : "v"(x0), "v"(x1), "v"(x2), "v"(x3), "v"(gq), "i"(Q));
 }
 
 // ------------------------------------------------------------- reductions
@@ -372,9 +387,20 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                 }
                 // The numerators scaled by the inverse diagonal, tau = t / G_kk
                 // (the step of the closed form before projection).
-                double4v t = tcur;
+                double t0 = tcur[0] * inv[b], t1 = tcur[1] * inv[b];
+                double t2 = tcur[2] * inv[b], t3 = tcur[3] * inv[b];
+                // The block's in-block Gram column entries, all read before
+                // the first step: the empty asm takes them as in/out operands,
+                // so the compiler can neither sink each read to its step (and
+                // wait on it there) nor read them again.
+                double gqv[16];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) t[v] *= inv[b];
+                for (int q = 0; q < 16; ++q) gqv[q] = s_tri[b][q][lr];
+                asm volatile(""
+                             : "+v"(gqv[0]), "+v"(gqv[1]), "+v"(gqv[2]), "+v"(gqv[3]),
+                               "+v"(gqv[4]), "+v"(gqv[5]), "+v"(gqv[6]), "+v"(gqv[7]),
+                               "+v"(gqv[8]), "+v"(gqv[9]), "+v"(gqv[10]), "+v"(gqv[11]),
+                               "+v"(gqv[12]), "+v"(gqv[13]), "+v"(gqv[14]), "+v"(gqv[15]));
                 // Coordinates 16b .. 16b+15 in order. Every lane forms the
                 // change its coordinate would take; lane q's is the one used
                 // at step q, and the later coordinates correct their tau. Lanes
@@ -386,22 +412,17 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                 static_for<16>([&](auto Q) {
                     constexpr int q = decltype(Q)::value;
                     if (b + 1 < NB || 16 * b + q < a.r) {
-                        const double gq = s_tri[b][q][lr];
-                        // Stage by stage over the four independent rows of
-                        // the lane, so that their latencies overlap.
                         // The change max(x + tau, 0) - x, formed as
-                        // max(tau, -x): equal up to rounding, shorter.
-                        double d[4];
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) d[v] = fmax(t[v], -xd[b][v]);
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) d[v] = row_bcast<q>(d[v]);
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) t[v] = fma(-gq, d[v], t[v]);
+                        // max(tau, -x): equal up to rounding, shorter. The
+                        // four independent rows of the lane go stage by
+                        // stage, so that their latencies overlap.
+                        step4<q>(t0, t1, t2, t3, xd[b][0], xd[b][1], xd[b][2], xd[b][3], gqv[q]);
                     }
                 });
-#pragma unroll
-                for (int v = 0; v < 4; ++v) xd[b][v] = fmax(xd[b][v] + t[v], 0.0);
+                xd[b][0] = fmax(xd[b][0] + t0, 0.0);
+                xd[b][1] = fmax(xd[b][1] + t1, 0.0);
+                xd[b][2] = fmax(xd[b][2] + t2, 0.0);
+                xd[b][3] = fmax(xd[b][3] + t3, 0.0);
                 // The block's new values into A layout (wave-private LDS tile;
                 // the LDS operations of a wave complete in order).
 #pragma unroll
