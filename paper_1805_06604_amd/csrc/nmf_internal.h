@@ -33,9 +33,13 @@ constexpr int kX16Rows = 256;
 constexpr int kRowsPerBlock = 64;
 
 // Per-workgroup record of the sweep kernels: up to two partial Gram matrices
-// with their column maxima, and three FP64 partial sums (<W, A>, and the
-// numerator and denominator of the beta* diagnostic).
-__host__ __device__ constexpr int64_t sweep_record(int rp) { return 2 * (rp * rp + rp) + 3; }
+// (their 16 x 16 blocks on and above the diagonal) with their column maxima,
+// and three FP64 partial sums (<W, A>, and the numerator and denominator of
+// the beta* diagnostic).
+__host__ __device__ constexpr int64_t sweep_record(int rp)
+{
+    return 2 * ((rp / 16) * (rp / 16 + 1) / 2 * 256 + rp) + 3;
+}
 
 // Slot selectors for the product kernels.
 enum FactorSel : int32_t {

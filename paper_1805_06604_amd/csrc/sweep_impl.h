@@ -48,11 +48,22 @@ struct ModeInfo {
     static constexpr int ngram = (M == SWEEP_W) ? 2 : 1;
 };
 
-// Per-workgroup record: ngram x (RP*RP Gram entries, RP column maxima), then
-// <x, c> and the numerator and denominator of the beta* diagnostic.
+// Per-workgroup record: ngram x (the Gram's 16 x 16 blocks on and above the
+// diagonal, block rows in order and each block row from its diagonal block
+// on, 256 entries each in row-major order; then RP column maxima), then
+// <x, c> and the numerator and denominator of the beta* diagnostic. The
+// Gram is symmetric: the blocks below the diagonal are the transposes of
+// those above and are written by the finish kernels from them.
 constexpr int kRecTail = 3;
+__host__ __device__ constexpr int gram_blocks(int rp) { return (rp / 16) * (rp / 16 + 1) / 2; }
+__host__ __device__ constexpr int rec_gram_len(int rp) { return gram_blocks(rp) * 256 + rp; }
 template <int RP>
-__host__ __device__ constexpr int rec_len(int ngram) { return ngram * (RP * RP + RP) + kRecTail; }
+__host__ __device__ constexpr int rec_len(int ngram) { return ngram * rec_gram_len(RP) + kRecTail; }
+// Index of block (b1, b2), b1 <= b2, among the stored blocks.
+__host__ __device__ constexpr int gram_block_index(int nb, int b1, int b2)
+{
+    return b1 * nb - b1 * (b1 - 1) / 2 + (b2 - b1);
+}
 
 // Solver flags read on the device (the NMF_FLAG_* values of the C ABI).
 constexpr int kFlagBetaStar = 4;
@@ -562,32 +573,38 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
             mx = fmax(mx, __shfl_xor(mx, 32));
             if (g == 0) s_cm[wave][gi * RP + 16 * b + lr] = mx;
         }
-        // Partial Gram, one block row b1 at a time: G(16b1 + i, 16b2 + j) =
-        // sum over the wave's 16 rows of w(row, 16b1+i) w(row, 16b2+j).
+        // Partial Gram, one block row b1 at a time, the blocks b2 >= b1 only:
+        // G(16b1 + i, 16b2 + j) = sum over the wave's 16 rows of
+        // w(row, 16b1+i) w(row, 16b2+j).
+        double *rg = rec + gi * rec_gram_len(RP);
         static_for<NB>([&](auto B1) {
             constexpr int b1 = decltype(B1)::value;
-            double4v acc[NB];
+            constexpr int NC = NB - b1;      // blocks b1 .. NB-1 of the row
+            double4v acc[NC];
 #pragma unroll
-            for (int b2 = 0; b2 < NB; ++b2) {
-                acc[b2] = double4v{0.0, 0.0, 0.0, 0.0};
+            for (int c = 0; c < NC; ++c) {
+                acc[c] = double4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    acc[b2] = __builtin_amdgcn_mfma_f64_16x16x4f64(gw[gi][b1][v], gw[gi][b2][v],
-                                                                   acc[b2], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(gw[gi][b1][v], gw[gi][b1 + c][v],
+                                                                  acc[c], 0, 0, 0);
             }
             __syncthreads();                 // s_buf free (sweep tiles, previous row)
 #pragma unroll
-            for (int b2 = 0; b2 < NB; ++b2)
+            for (int c = 0; c < NC; ++c)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) s_buf[((wave * NB + b2) * 4 + v) * 64 + lane] = acc[b2][v];
+                for (int v = 0; v < 4; ++v) s_buf[((wave * NB + c) * 4 + v) * 64 + lane] = acc[c][v];
             __syncthreads();
-            for (int e = tid; e < NB * 256; e += kThreads) {
-                const int b2 = e >> 8, v = (e >> 6) & 3, ln = e & 63;
+            // Entry e of the row's stored blocks: block b1 + (e >> 8), rows
+            // 4v + (ln >> 4), column ln & 15, i.e. offset e from the row's
+            // first stored block.
+            double *rb = rg + gram_block_index(NB, b1, b1) * 256;
+            for (int e = tid; e < NC * 256; e += kThreads) {
+                const int c = e >> 8, v = (e >> 6) & 3, ln = e & 63;
                 double sum = 0.0;
 #pragma unroll
-                for (int w = 0; w < kWaves; ++w) sum += s_buf[((w * NB + b2) * 4 + v) * 64 + ln];
-                const int i = 16 * b1 + 4 * v + (ln >> 4), j = 16 * b2 + (ln & 15);
-                rec[gi * (RP * RP + RP) + i * RP + j] = sum;
+                for (int w = 0; w < kWaves; ++w) sum += s_buf[((w * NB + c) * 4 + v) * 64 + ln];
+                rb[e] = sum;
             }
         });
     }
@@ -610,7 +627,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
 #pragma unroll
         for (int w = 1; w < kWaves; ++w) mx = fmax(mx, s_cm[w][e]);
         const int gi = e / RP, k = e % RP;
-        rec[gi * (RP * RP + RP) + RP * RP + k] = mx;
+        rec[gi * rec_gram_len(RP) + gram_blocks(RP) * 256 + k] = mx;
     }
     if (tid < kRecTail) {
         double v = 0.0;
@@ -636,8 +653,9 @@ struct FinArgs {
 
 // Sums the per-workgroup records (64 outputs per workgroup, each over 4
 // interleaved strides of records, combined in a fixed order) into the Gram
-// buffers: Gram, inverse diagonal (0 beyond r or for a zero diagonal) and
-// column maxima. The last workgroup then forms e(k) and decides (W sides).
+// buffers: Gram (an entry above the diagonal blocks also into its mirror
+// below), inverse diagonal (0 beyond r or for a zero diagonal) and column
+// maxima. The last workgroup then forms e(k) and decides (W sides).
 constexpr int kFinOut = 64;
 constexpr int kFinSplit = 4;
 
@@ -647,17 +665,21 @@ constexpr int kFinSplit = 4;
 template <int RP, int MODE>
 __device__ __forceinline__ void fin_store(const FinArgs &a, const int *slot, int e, double s)
 {
-    constexpr int NG = ModeInfo<MODE>::ngram;
-    constexpr int GL = RP * RP + RP;
+    constexpr int NG = ModeInfo<MODE>::ngram, NB = RP / 16;
+    constexpr int GL = rec_gram_len(RP), GB = gram_blocks(RP) * 256;
     if (e < NG * GL) {
         const int gi = e / GL, w = e % GL;
         double *Gd = a.gram + slot[gi] * a.gram_slot_stride;
-        if (w < RP * RP) {
-            Gd[w] = s;
-            const int k = w / RP, l = w % RP;
+        if (w < GB) {
+            int u = w >> 8, b1 = 0;
+            while (u >= NB - b1) u -= NB - b1++;
+            const int b2 = b1 + u;
+            const int k = 16 * b1 + ((w >> 4) & 15), l = 16 * b2 + (w & 15);
+            Gd[k * RP + l] = s;
+            if (b1 != b2) Gd[l * RP + k] = s;
             if (k == l) Gd[RP * RP + k] = (k < a.r && s > 0.0) ? 1.0 / s : 0.0;
         } else {
-            Gd[RP * RP + RP + (w - RP * RP)] = s;
+            Gd[RP * RP + RP + (w - GB)] = s;
         }
     } else if (ModeInfo<MODE>::s1) {
         a.scratch[e - NG * GL] = s;        // <x, c>, beta* numerator, denominator
@@ -714,7 +736,7 @@ template <int RP, int MODE>
 __device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
 {
     constexpr int NG = ModeInfo<MODE>::ngram;
-    constexpr int GL = RP * RP + RP;
+    constexpr int GL = rec_gram_len(RP);
     constexpr int LREC = rec_len<RP>(NG);
     __shared__ double sh[kFinSplit][kFinOut];
     __shared__ double shd[4];
@@ -727,7 +749,7 @@ __device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
     fin_slots<RP, MODE>(st, slot);
     const int o = threadIdx.x & (kFinOut - 1), j = threadIdx.x / kFinOut;
     const int e = bid * kFinOut + o;
-    const bool is_max = e < NG * GL && (e % GL) >= RP * RP;
+    const bool is_max = e < NG * GL && (e % GL) >= gram_blocks(RP) * 256;
     double v = 0.0;
     if (e < LREC) {
         const double *src = a.part + e;
@@ -759,7 +781,7 @@ template <int RP, int MODE>
 __device__ __forceinline__ void finish_sum_body(const FinArgs &a, int bid)
 {
     constexpr int NG = ModeInfo<MODE>::ngram;
-    constexpr int GL = RP * RP + RP;
+    constexpr int GL = rec_gram_len(RP);
     constexpr int LREC = rec_len<RP>(NG);
     __shared__ double sh[kFinSplit][kFinOut];
     DevState *st = a.st;
@@ -768,7 +790,7 @@ __device__ __forceinline__ void finish_sum_body(const FinArgs &a, int bid)
     fin_slots<RP, MODE>(st, slot);
     const int o = threadIdx.x & (kFinOut - 1), j = threadIdx.x / kFinOut;
     const int e = bid * kFinOut + o;
-    const bool is_max = e < NG * GL && (e % GL) >= RP * RP;
+    const bool is_max = e < NG * GL && (e % GL) >= gram_blocks(RP) * 256;
     double v = 0.0;
     if (e < LREC) {
         const double *src = a.part + e;
@@ -951,7 +973,7 @@ inline FinArgs fin_args(int rp, int64_t rows, int r, const Buffers &b, bool w_si
 
 // Blocks of the two kernels of a half-iteration.
 inline int hals_blocks(int64_t rows) { return (int)((rows + kRows - 1) / kRows); }
-inline int fin_blocks(int rp, int ngram) { return (int)((ngram * (rp * rp + rp) + kRecTail + kFinOut - 1) / kFinOut); }
+inline int fin_blocks(int rp, int ngram) { return (int)((ngram * rec_gram_len(rp) + kRecTail + kFinOut - 1) / kFinOut); }
 
 // Enqueues one half-iteration (or a set-up step) of one padded rank.
 template <int RP>
