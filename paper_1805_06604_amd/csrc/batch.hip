@@ -139,7 +139,6 @@ size_t layout(Prob &q, char *base)
     b.Ct = (double *)take(sizeof(double) * q.pc.nsplit * q.n_pad * rp);
     b.part_g = (double *)take(sizeof(double) * nblk * nmf::sweep_record(q.rp));
     b.part_d = (double *)take(sizeof(double) * 1024);
-    b.counters = (uint32_t *)take(sizeof(uint32_t) * nmf::CNT_N);
     b.st = (DevState *)take(sizeof(DevState));
     b.trace = (double *)take(sizeof(double) * (q.p.max_iter + 1));
     b.accepted = (uint8_t *)take((size_t)q.p.max_iter + 1);
@@ -370,8 +369,8 @@ nmf_status rebuild(nmf_batch *B)
                 E.hh.K = E.hw.K = 0;
                 E.hh.src_mode = E.hw.src_mode = 1;
             }
-            E.fh = nmf::sweep::fin_args(rp, q.n, q.r, q.b, false, q.b.counters + nmf::CNT_H);
-            E.fw = nmf::sweep::fin_args(rp, q.m, q.r, q.b, true, q.b.counters + nmf::CNT_W);
+            E.fh = nmf::sweep::fin_args(rp, q.n, q.r, q.b, false);
+            E.fw = nmf::sweep::fin_args(rp, q.m, q.r, q.b, true);
             const int nb[kKinds] = {(int)(q.pc.ld / 64), (int)(q.pc.rows_pad / 128 * q.pc.nsplit),
                                     nmf::sweep::hals_blocks(q.n), nmf::sweep::fin_blocks(rp, 1),
                                     (int)(q.pa.ld / 64), (int)(q.pa.rows_pad / 128 * q.pa.nsplit),
@@ -411,8 +410,9 @@ Group group_of(nmf_batch *B, int c, int kind, size_t member_offset)
 }
 
 // Fixed grids of the grouped kernels (workgroups walk the work blocks with a
-// grid stride): about one resident round of the chip per kernel kind.
-constexpr int kGrid[kKinds] = {1024, 256, 512, 1024, 1024, 256, 512, 1024, 512, 512, 512};
+// grid stride): about one resident round of the chip per kernel kind (the
+// finish and decision kernels have 1024 threads per workgroup).
+constexpr int kGrid[kKinds] = {1024, 256, 512, 512, 1024, 256, 512, 512, 512, 512, 512};
 
 // One batch iteration of padded-rank class c on stream cs: both products,
 // the exact solves (a no-op without E-ANLS problems) and both sweep steps.

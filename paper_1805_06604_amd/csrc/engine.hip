@@ -273,7 +273,7 @@ void free_all(nmf_ctx *c)
     for (void *p : c->extra)
         if (p) (void)hipFree(p);
     void *ptrs[] = {c->X, c->Xt, c->zexp_x, c->zexp_xt, c->b.Wf, c->b.Hf, c->b.GW, c->b.GH,
-                    c->b.A, c->b.Ct, c->b.part_g, c->b.part_d, c->b.counters, c->b.st, c->b.trace,
+                    c->b.A, c->b.Ct, c->b.part_g, c->b.part_d, c->b.st, c->b.trace,
                     c->b.accepted, c->b.beta_used, c->b.beta_star, c->b.stage, c->b.fsl, c->b.texp,
                     c->b.x64, c->b.part_n, c->b.sweeps, c->b.ginv_h, c->b.ginv_w,
                     c->e2_scale};
@@ -314,8 +314,6 @@ nmf_status alloc_buffers(nmf_ctx *c)
     c->pc.Y = b.Ct;
     HIP_TRY(c, dalloc(&b.part_g, (size_t)(nblk * rec)));
     HIP_TRY(c, dalloc(&b.part_d, (size_t)1024));
-    HIP_TRY(c, dalloc(&b.counters, (size_t)nmf::CNT_N));
-    HIP_TRY(c, hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * nmf::CNT_N, c->own));
     HIP_TRY(c, dalloc(&b.st, 1));
     HIP_TRY(c, dalloc(&b.trace, (size_t)c->p.max_iter + 1));
     HIP_TRY(c, dalloc(&b.accepted, (size_t)c->p.max_iter));
@@ -778,7 +776,6 @@ nmf_status nmf_start(nmf_ctx *c, const float *W0, const float *H0, int32_t on_de
     const int rp = c->rp;
     Buffers &b = c->b;
     HIP_TRY(c, hipMemcpyAsync(b.st, &h, sizeof(h), hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * nmf::CNT_N, s));
     HIP_TRY(c, nmf::launch_pack(rp, m, n, r, w0, h0, b, s));
     HIP_TRY(c, nmf::launch_setup_gram_h(rp, n, r, b, s));
     nmf::ProdArgs a0 = c->pa;

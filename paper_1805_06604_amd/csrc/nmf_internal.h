@@ -181,7 +181,6 @@ struct Buffers {
     int64_t m_pad = 0, n_pad = 0;
     double *part_g = nullptr;// per-workgroup records of the sweep kernels
     double *part_d = nullptr;// FP64 scratch: reduction partials, the summed <W, A>
-    uint32_t *counters = nullptr; // last-block counters (zeroed; reset by the kernels)
     DevState *st = nullptr;
     double *trace = nullptr; // max_iter + 1
     uint8_t *accepted = nullptr;
@@ -200,9 +199,6 @@ struct Buffers {
     double *part_n = nullptr;
     int32_t *sweeps = nullptr;
 };
-
-// Last-block counters, one per kernel kind, each on its own 256-byte line.
-enum Counter { CNT_H = 0, CNT_W = 64, CNT_G = 128, CNT_N = 192 };
 
 // A grouped launch runs one kernel over several problems at once: problem p
 // owns the work blocks prefix[p] .. prefix[p + 1] - 1 and reads its argument

@@ -111,7 +111,6 @@ size_t carve(Plan &q, const nmf_params &p, char *base, uint8_t *accepted, double
     b.Ct = (double *)take(sizeof(double) * q.pc.nsplit * q.n_pad * rp);
     b.part_g = (double *)take(sizeof(double) * nblk * nmf::sweep_record(q.rp));
     b.part_d = (double *)take(sizeof(double) * 1024);
-    b.counters = (uint32_t *)take(sizeof(uint32_t) * nmf::CNT_N);
     b.st = (nmf::DevState *)take(sizeof(nmf::DevState));
     b.accepted = accepted ? accepted : (uint8_t *)take(iters);
     b.beta_used = beta ? beta : (double *)take(sizeof(double) * iters);
@@ -190,7 +189,7 @@ extern "C" nmf_status nmf_solve_noalloc(const float *X, int64_t m, int64_t n,
     const int rp = q.rp, r = q.r;
 
     // Everything carved starts at zero (padding of X, of the factor slots
-    // and of the products, the last-block counters).
+    // and of the products).
     const size_t n16 = need / 16;
     zero_kernel<<<(unsigned)std::min<size_t>((n16 + 255) / 256, 8192), 256, 0, s>>>(
         static_cast<uint4 *>(base), n16);

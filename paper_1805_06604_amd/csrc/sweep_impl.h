@@ -13,9 +13,11 @@
 //    (DPP row_newbcast). The epilogue stores the new factor rows and the
 //    extrapolated rows, and writes one record per workgroup: the partial Gram
 //    matrices (FP64 matrix cores again), column maxima and <W_n, A>.
-//  * finish_kernel: sums the records in a fixed order (deterministic), writes
-//    the Gram matrices with their inverse diagonals and column maxima, and in
-//    its last workgroup forms the error of Remark 1 and takes the decision.
+//  * finish_kernel: sums the records in a fixed order (deterministic) and
+//    writes the Gram matrices with their inverse diagonals and column maxima;
+//    on W sides a one-workgroup decide_kernel follows (the launch boundary
+//    makes the sums visible), which forms the error of Remark 1 and takes the
+//    decision.
 //
 // Register layout of the 16 x 16 tiles (16 rows of a wave, 16 coordinates):
 // lane l = lr + 16 g holds, in its 4 values v, rows 4 v + g of coordinate lr
@@ -108,32 +110,25 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return t;
 }
 
-// Marks this block done; returns true in every thread of the last block to
-// finish. The block's results must have been written by wave 0 only (which
-// alone makes them visible before the count). The blocks of a grid run on all
-// XCDs, whose L2 caches are not coherent with one another, so the counter is
-// updated at system scope (coherent at memory); the fences write back and
-// invalidate the L2 for the data.
-__device__ inline bool last_block(uint32_t *counter, int *s_flag, int nblk)
+// Sum over a workgroup of NW waves (the finish kernels), lane order within a
+// wave, then the waves pairwise in a fixed tree; sh holds NW doubles.
+template <int NW>
+__device__ __forceinline__ double block_sum_n(double v, double *sh)
 {
-    if (threadIdx.x < 64) __threadfence();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) sh[wave] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t prev =
-            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
-        *s_flag = (prev == (uint32_t)nblk - 1);
-    }
+    double t[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t[w] = sh[w];
+#pragma unroll
+    for (int h = NW / 2; h > 0; h /= 2)
+#pragma unroll
+        for (int w = 0; w < h; ++w) t[w] = t[w] + t[w + h];
     __syncthreads();
-    const bool last = *s_flag != 0;
-    if (last) __threadfence();
-    return last;
-}
-
-// Re-arms a last-block counter for the next launch (system scope, like the
-// increments).
-__device__ inline void reset_counter(uint32_t *counter)
-{
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    return t[0];
 }
 
 // ------------------------------------------------------ decision (a8 row)
@@ -643,7 +638,6 @@ struct FinArgs {
     int64_t gram_slot_stride;
     const double *GH;      // Gram of H_w (W sides: s2)
     double *scratch;       // the summed <x, c>, beta* numerator and denominator
-    uint32_t *counter;
     DevState *st;
     double *trace;
     uint8_t *accepted;
@@ -651,13 +645,17 @@ struct FinArgs {
     double *beta_star;
 };
 
-// Sums the per-workgroup records (64 outputs per workgroup, each over 4
-// interleaved strides of records, combined in a fixed order) into the Gram
-// buffers: Gram (an entry above the diagonal blocks also into its mirror
-// below), inverse diagonal (0 beyond r or for a zero diagonal) and column
-// maxima. The last workgroup then forms e(k) and decides (W sides).
+// Sums the per-workgroup records (64 outputs per workgroup of 1024 threads,
+// each output over 16 interleaved strides of records, one per wave, so that
+// a thread's chain of record loads is short; the 16 partial sums combined in
+// a fixed order) into the Gram buffers: Gram (an entry above the diagonal
+// blocks also into its mirror below), inverse diagonal (0 beyond r or for a
+// zero diagonal) and column maxima. On W sides a second launch of one
+// workgroup then forms e(k) and decides.
 constexpr int kFinOut = 64;
-constexpr int kFinSplit = 4;
+constexpr int kFinThreads = 1024;
+constexpr int kFinSplit = kFinThreads / kFinOut;
+constexpr int kFinWaves = kFinThreads / 64;
 
 // Destination of output e of the records: the Gram entry (and the inverse
 // diagonal beside a diagonal entry), a column maximum, or one of the scalars
@@ -695,8 +693,8 @@ __device__ __forceinline__ void fin_decide(const FinArgs &a, const int *slot, do
         DevState *st = a.st;
         const double *Gn = a.gram + slot[0] * a.gram_slot_stride;
         double s2 = 0.0;
-        for (int q = threadIdx.x; q < RP * RP; q += 256) s2 = fma(Gn[q], a.GH[q], s2);
-        s2 = block_sum(s2, shd);
+        for (int q = threadIdx.x; q < RP * RP; q += kFinThreads) s2 = fma(Gn[q], a.GH[q], s2);
+        s2 = block_sum_n<kFinWaves>(s2, shd);
         if (threadIdx.x == 0) {
             const double s1 = a.scratch[0];
             if constexpr (MODE == SWEEP_W) {
@@ -732,51 +730,9 @@ __device__ __forceinline__ void fin_slots(const DevState *st, int *slot)
     }
 }
 
-template <int RP, int MODE>
-__device__ __forceinline__ void finish_body(const FinArgs &a, int bid, int nblk)
-{
-    constexpr int NG = ModeInfo<MODE>::ngram;
-    constexpr int GL = rec_gram_len(RP);
-    constexpr int LREC = rec_len<RP>(NG);
-    __shared__ double sh[kFinSplit][kFinOut];
-    __shared__ double shd[4];
-    __shared__ int s_last;
-    DevState *st = a.st;
-    int slot[NG];
-    if constexpr (MODE == SWEEP_H || MODE == SWEEP_W) {
-        if (st->done) return;
-    }
-    fin_slots<RP, MODE>(st, slot);
-    const int o = threadIdx.x & (kFinOut - 1), j = threadIdx.x / kFinOut;
-    const int e = bid * kFinOut + o;
-    const bool is_max = e < NG * GL && (e % GL) >= gram_blocks(RP) * 256;
-    double v = 0.0;
-    if (e < LREC) {
-        const double *src = a.part + e;
-#pragma unroll 8
-        for (int b = j; b < a.nblk; b += kFinSplit) {
-            const double x = src[(size_t)b * LREC];
-            v = is_max ? fmax(v, x) : v + x;
-        }
-    }
-    sh[j][o] = v;
-    __syncthreads();
-    if (j == 0 && e < LREC) {          // wave 0
-        double s = sh[0][o];
-#pragma unroll
-        for (int q = 1; q < kFinSplit; ++q) s = is_max ? fmax(s, sh[q][o]) : s + sh[q][o];
-        fin_store<RP, MODE>(a, slot, e, s);
-    }
-    if (!last_block(a.counter, &s_last, nblk)) return;
-    fin_decide<RP, MODE>(a, slot, shd);
-    if (threadIdx.x == 0) reset_counter(a.counter);
-}
-
-// The same two steps as two launches, for batched problems: finish_sum_body
-// is the summing part of finish_body (kFinOut outputs per work block, the
-// same order of records), with no completion counter and no cross-workgroup
-// fence; finish_decide_body, one work block per problem in the next launch
-// (the launch boundary makes the sums visible), is its decision part.
+// The summing step (kFinOut outputs per work block) and, in the next launch
+// (whose boundary makes the sums visible), the decision step of one work
+// block per problem; neither has a cross-workgroup fence.
 template <int RP, int MODE>
 __device__ __forceinline__ void finish_sum_body(const FinArgs &a, int bid)
 {
@@ -786,7 +742,9 @@ __device__ __forceinline__ void finish_sum_body(const FinArgs &a, int bid)
     __shared__ double sh[kFinSplit][kFinOut];
     DevState *st = a.st;
     int slot[NG];
-    if (st->done) return;
+    if constexpr (ModeInfo<MODE>::sweeps) {
+        if (st->done) return;        // set-up launches always run
+    }
     fin_slots<RP, MODE>(st, slot);
     const int o = threadIdx.x & (kFinOut - 1), j = threadIdx.x / kFinOut;
     const int e = bid * kFinOut + o;
@@ -794,7 +752,7 @@ __device__ __forceinline__ void finish_sum_body(const FinArgs &a, int bid)
     double v = 0.0;
     if (e < LREC) {
         const double *src = a.part + e;
-#pragma unroll 8
+#pragma unroll 16
         for (int b = j; b < a.nblk; b += kFinSplit) {
             const double x = src[(size_t)b * LREC];
             v = is_max ? fmax(v, x) : v + x;
@@ -814,10 +772,12 @@ template <int RP, int MODE>
 __device__ __forceinline__ void finish_decide_body(const FinArgs &a)
 {
     constexpr int NG = ModeInfo<MODE>::ngram;
-    __shared__ double shd[4];
+    __shared__ double shd[kFinWaves];
     DevState *st = a.st;
     int slot[NG];
-    if (st->done) return;
+    if constexpr (ModeInfo<MODE>::sweeps) {
+        if (st->done) return;        // set-up launches always run
+    }
     fin_slots<RP, MODE>(st, slot);
     fin_decide<RP, MODE>(a, slot, shd);
 }
@@ -865,9 +825,16 @@ __global__ __launch_bounds__(kThreads, 1) void hals_kernel(HalsArgs a)
 }
 
 template <int RP, int MODE>
-__global__ __launch_bounds__(256) void finish_kernel(FinArgs a)
+__global__ __launch_bounds__(kFinThreads) void finish_kernel(FinArgs a)
 {
-    finish_body<RP, MODE>(a, blockIdx.x, gridDim.x);
+    finish_sum_body<RP, MODE>(a, blockIdx.x);
+}
+
+// One workgroup: s2, then e(k) and the decision (W sweep) or e(0) (W set-up).
+template <int RP, int MODE>
+__global__ __launch_bounds__(kFinThreads) void decide_kernel(FinArgs a)
+{
+    finish_decide_body<RP, MODE>(a);
 }
 
 // Grouped forms: one launch over several problems of the same padded rank
@@ -887,7 +854,7 @@ __global__ __launch_bounds__(kThreads, 1) void hals_group_kernel(Group g)
 }
 
 template <int RP, int MODE>
-__global__ __launch_bounds__(256) void finish_group_kernel(Group g)
+__global__ __launch_bounds__(kFinThreads) void finish_group_kernel(Group g)
 {
     const int total = group_total(g);
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
@@ -900,7 +867,7 @@ __global__ __launch_bounds__(256) void finish_group_kernel(Group g)
 
 // One work block per problem.
 template <int RP, int MODE>
-__global__ __launch_bounds__(256) void decide_group_kernel(Group g)
+__global__ __launch_bounds__(kFinThreads) void decide_group_kernel(Group g)
 {
     const int total = group_total(g);
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
@@ -952,7 +919,7 @@ inline HalsArgs hals_args(int rp, int64_t rows, int r, int K, const Buffers &b, 
     return h;
 }
 
-inline FinArgs fin_args(int rp, int64_t rows, int r, const Buffers &b, bool w_side, uint32_t *counter)
+inline FinArgs fin_args(int rp, int64_t rows, int r, const Buffers &b, bool w_side)
 {
     FinArgs f{};
     f.part = b.part_g;
@@ -962,7 +929,6 @@ inline FinArgs fin_args(int rp, int64_t rows, int r, const Buffers &b, bool w_si
     f.gram_slot_stride = w_side ? gram_stride(rp) : 0;
     f.GH = b.GH;
     f.scratch = b.part_d;
-    f.counter = counter;
     f.st = b.st;
     f.trace = b.trace;
     f.accepted = b.accepted;
@@ -981,10 +947,9 @@ struct Launch {
     // exact (sweep modes): the exact NNLS solve, then the sweep kernel with
     // no sweeps for the epilogue.
     template <int MODE>
-    static void run(int64_t rows, int r, int K, const Buffers &b, bool w_side, uint32_t *counter,
-                    hipStream_t s, hipEvent_t mid = nullptr, bool exact = false)
+    static void run(int64_t rows, int r, int K, const Buffers &b, bool w_side, hipStream_t s,
+                    hipEvent_t mid = nullptr, bool exact = false)
     {
-        constexpr int NG = ModeInfo<MODE>::ngram;
         HalsArgs h = hals_args(RP, rows, r, K, b, w_side);
         if constexpr (ModeInfo<MODE>::sweeps) {
             if (exact) {
@@ -995,8 +960,17 @@ struct Launch {
         }
         hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
         if (mid) (void)hipEventRecord(mid, s);
-        const FinArgs f = fin_args(RP, rows, r, b, w_side, counter);
-        finish_kernel<RP, MODE><<<fin_blocks(RP, NG), 256, 0, s>>>(f);
+        finish<MODE>(rows, r, b, w_side, s);
+    }
+    // The finish launch of a half-iteration, and the decision launch of the
+    // W sides.
+    template <int MODE>
+    static void finish(int64_t rows, int r, const Buffers &b, bool w_side, hipStream_t s)
+    {
+        constexpr int NG = ModeInfo<MODE>::ngram;
+        const FinArgs f = fin_args(RP, rows, r, b, w_side);
+        finish_kernel<RP, MODE><<<fin_blocks(RP, NG), kFinThreads, 0, s>>>(f);
+        if constexpr (ModeInfo<MODE>::s1) decide_kernel<RP, MODE><<<1, kFinThreads, 0, s>>>(f);
     }
     // Grouped half-iteration: the sweep kernel over group gh, then the
     // summing finish kernel over group gf (and, W side, the decision).
@@ -1012,11 +986,11 @@ struct Launch {
     {
         if (w_side) {
             hals_group_kernel<RP, SWEEP_W><<<hblocks, kThreads, 0, s>>>(gh);
-            finish_group_kernel<RP, SWEEP_W><<<fblocks, 256, 0, s>>>(gf);
-            decide_group_kernel<RP, SWEEP_W><<<dblocks, 256, 0, s>>>(gd);
+            finish_group_kernel<RP, SWEEP_W><<<fblocks, kFinThreads, 0, s>>>(gf);
+            decide_group_kernel<RP, SWEEP_W><<<dblocks, kFinThreads, 0, s>>>(gd);
         } else {
             hals_group_kernel<RP, SWEEP_H><<<hblocks, kThreads, 0, s>>>(gh);
-            finish_group_kernel<RP, SWEEP_H><<<fblocks, 256, 0, s>>>(gf);
+            finish_group_kernel<RP, SWEEP_H><<<fblocks, kFinThreads, 0, s>>>(gf);
         }
     }
     // Half-iteration with the adaptive inner loop: `cap` single-sweep launches,
@@ -1025,9 +999,8 @@ struct Launch {
     // the epilogue, and the finish kernel.
     template <int MODE>
     static void adaptive(int64_t rows, int r, int cap, double delta, const Buffers &b, bool w_side,
-                         uint32_t *counter, hipStream_t s, hipEvent_t mid)
+                         hipStream_t s, hipEvent_t mid)
     {
-        constexpr int NG = ModeInfo<MODE>::ngram;
         HalsArgs h = hals_args(RP, rows, r, 1, b, w_side);
         h.x64 = b.x64;
         h.part_n = b.part_n;
@@ -1043,18 +1016,17 @@ struct Launch {
         h.src_mode = 2;
         hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
         if (mid) (void)hipEventRecord(mid, s);
-        const FinArgs fa = fin_args(RP, rows, r, b, w_side, counter);
-        finish_kernel<RP, MODE><<<fin_blocks(RP, NG), 256, 0, s>>>(fa);
+        finish<MODE>(rows, r, b, w_side, s);
     }
     static void sweep_h_adaptive(int64_t n, int r, int cap, double delta, const Buffers &b,
                                  hipStream_t s, hipEvent_t mid)
     {
-        adaptive<SWEEP_H>(n, r, cap, delta, b, false, b.counters + CNT_H, s, mid);
+        adaptive<SWEEP_H>(n, r, cap, delta, b, false, s, mid);
     }
     static void sweep_w_adaptive(int64_t m, int r, int cap, double delta, const Buffers &b,
                                  hipStream_t s, hipEvent_t mid)
     {
-        adaptive<SWEEP_W>(m, r, cap, delta, b, true, b.counters + CNT_W, s, mid);
+        adaptive<SWEEP_W>(m, r, cap, delta, b, true, s, mid);
     }
     static void invert(bool w_side, int r, const Buffers &b, hipStream_t s)
     {
@@ -1065,20 +1037,20 @@ struct Launch {
     static void sweep_h(int64_t n, int r, int K, bool exact, const Buffers &b, hipStream_t s,
                         hipEvent_t mid)
     {
-        run<SWEEP_H>(n, r, K, b, false, b.counters + CNT_H, s, mid, exact);
+        run<SWEEP_H>(n, r, K, b, false, s, mid, exact);
     }
     static void sweep_w(int64_t m, int r, int K, bool exact, const Buffers &b, hipStream_t s,
                         hipEvent_t mid)
     {
-        run<SWEEP_W>(m, r, K, b, true, b.counters + CNT_W, s, mid, exact);
+        run<SWEEP_W>(m, r, K, b, true, s, mid, exact);
     }
     static void setup_h(int64_t n, int r, const Buffers &b, hipStream_t s)
     {
-        run<SETUP_H>(n, r, 0, b, false, b.counters + CNT_G, s);
+        run<SETUP_H>(n, r, 0, b, false, s);
     }
     static void setup_err(int64_t m, int r, const Buffers &b, hipStream_t s)
     {
-        run<SETUP_W>(m, r, 0, b, true, b.counters + CNT_G, s);
+        run<SETUP_W>(m, r, 0, b, true, s);
     }
 };
 
