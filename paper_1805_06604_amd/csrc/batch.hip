@@ -410,9 +410,8 @@ Group group_of(nmf_batch *B, int c, int kind, size_t member_offset)
 }
 
 // Fixed grids of the grouped kernels (workgroups walk the work blocks with a
-// grid stride): about one resident round of the chip per kernel kind (the
-// finish and decision kernels have 1024 threads per workgroup).
-constexpr int kGrid[kKinds] = {1024, 256, 512, 512, 1024, 256, 512, 512, 512, 512, 512};
+// grid stride): about one resident round of the chip per kernel kind.
+constexpr int kGrid[kKinds] = {1024, 256, 512, 1024, 1024, 256, 512, 1024, 512, 512, 512};
 
 // One batch iteration of padded-rank class c on stream cs: both products,
 // the exact solves (a no-op without E-ANLS problems) and both sweep steps.

@@ -110,27 +110,6 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return t;
 }
 
-// Sum over a workgroup of NW waves (the finish kernels), lane order within a
-// wave, then the waves pairwise in a fixed tree; sh holds NW doubles.
-template <int NW>
-__device__ __forceinline__ double block_sum_n(double v, double *sh)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double t[NW];
-#pragma unroll
-    for (int w = 0; w < NW; ++w) t[w] = sh[w];
-#pragma unroll
-    for (int h = NW / 2; h > 0; h /= 2)
-#pragma unroll
-        for (int w = 0; w < h; ++w) t[w] = t[w] + t[w + h];
-    __syncthreads();
-    return t[0];
-}
-
 // ------------------------------------------------------ decision (a8 row)
 
 // Error, accept/restart (Algorithm 2) and beta update (Algorithm 3), run by
@@ -645,17 +624,20 @@ struct FinArgs {
     double *beta_star;
 };
 
-// Sums the per-workgroup records (64 outputs per workgroup of 1024 threads,
-// each output over 16 interleaved strides of records, one per wave, so that
-// a thread's chain of record loads is short; the 16 partial sums combined in
-// a fixed order) into the Gram buffers: Gram (an entry above the diagonal
-// blocks also into its mirror below), inverse diagonal (0 beyond r or for a
-// zero diagonal) and column maxima. On W sides a second launch of one
-// workgroup then forms e(k) and decides.
+// Sums the per-workgroup records (64 outputs per workgroup, each output over
+// 16 interleaved strides of records, the 16 partial sums combined in a fixed
+// order) into the Gram buffers: Gram (an entry above the diagonal blocks
+// also into its mirror below), inverse diagonal (0 beyond r or for a zero
+// diagonal) and column maxima. On W sides a second launch of one workgroup
+// then forms e(k) and decides. A single problem's finish uses 1024-thread
+// workgroups (a wave per stride: short load chains for its 256 records at
+// 16384 rows); the grouped finish of the batch engine walks many small work
+// blocks over a fixed grid and uses 256-thread workgroups (four strides per
+// wave), which keeps more workgroups, and more work blocks, in flight. Both
+// form the same sums, and so does the decision step.
 constexpr int kFinOut = 64;
 constexpr int kFinThreads = 1024;
-constexpr int kFinSplit = kFinThreads / kFinOut;
-constexpr int kFinWaves = kFinThreads / 64;
+constexpr int kFinGroupThreads = 256;
 
 // Destination of output e of the records: the Gram entry (and the inverse
 // diagonal beside a diagonal entry), a column maximum, or one of the scalars
@@ -686,15 +668,38 @@ __device__ __forceinline__ void fin_store(const FinArgs &a, const int *slot, int
 
 // After every output is stored and visible to the calling workgroup: s2,
 // then e(k) and the decision (W sweep), or e(0) (W set-up).
-template <int RP, int MODE>
+template <int RP, int MODE, int NT>
 __device__ __forceinline__ void fin_decide(const FinArgs &a, const int *slot, double *shd)
 {
     if constexpr (ModeInfo<MODE>::s1) {
         DevState *st = a.st;
         const double *Gn = a.gram + slot[0] * a.gram_slot_stride;
-        double s2 = 0.0;
-        for (int q = threadIdx.x; q < RP * RP; q += kFinThreads) s2 = fma(Gn[q], a.GH[q], s2);
-        s2 = block_sum_n<kFinWaves>(s2, shd);
+        // s2 = <Gn, GH> in the order of kFinThreads virtual threads, whatever
+        // the workgroup size NT: virtual thread t sums entries t, t + 1024,
+        // ... in order; each virtual wave is reduced across its lanes; the
+        // 16 wave sums are added in a fixed tree. Thread tid plays the
+        // virtual threads tid + k NT, which sit in the same lane of virtual
+        // waves tid / 64 + k NT / 64.
+        constexpr int NV = kFinThreads / NT, VW = kFinThreads / 64;
+        double part[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            part[k] = 0.0;
+            for (int q = threadIdx.x + k * NT; q < RP * RP; q += kFinThreads)
+                part[k] = fma(Gn[q], a.GH[q], part[k]);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) part[k] += __shfl_xor(part[k], off);
+            if ((threadIdx.x & 63) == 0) shd[(threadIdx.x >> 6) + k * (NT / 64)] = part[k];
+        }
+        __syncthreads();
+        double t[VW];
+#pragma unroll
+        for (int w = 0; w < VW; ++w) t[w] = shd[w];
+#pragma unroll
+        for (int h = VW / 2; h > 0; h /= 2)
+#pragma unroll
+            for (int w = 0; w < h; ++w) t[w] = t[w] + t[w + h];
+        const double s2 = t[0];
         if (threadIdx.x == 0) {
             const double s1 = a.scratch[0];
             if constexpr (MODE == SWEEP_W) {
@@ -733,12 +738,16 @@ __device__ __forceinline__ void fin_slots(const DevState *st, int *slot)
 // The summing step (kFinOut outputs per work block) and, in the next launch
 // (whose boundary makes the sums visible), the decision step of one work
 // block per problem; neither has a cross-workgroup fence.
-template <int RP, int MODE>
+template <int RP, int MODE, int NT>
 __device__ __forceinline__ void finish_sum_body(const FinArgs &a, int bid)
 {
     constexpr int NG = ModeInfo<MODE>::ngram;
     constexpr int GL = rec_gram_len(RP);
     constexpr int LREC = rec_len<RP>(NG);
+    // 16 record strides per output whatever the workgroup size: wave w of
+    // NT / 64 takes strides w, w + NT / 64, ... (the sums are the same for
+    // every NT).
+    constexpr int kFinSplit = kFinThreads / kFinOut, NW = NT / 64;
     __shared__ double sh[kFinSplit][kFinOut];
     DevState *st = a.st;
     int slot[NG];
@@ -746,21 +755,24 @@ __device__ __forceinline__ void finish_sum_body(const FinArgs &a, int bid)
         if (st->done) return;        // set-up launches always run
     }
     fin_slots<RP, MODE>(st, slot);
-    const int o = threadIdx.x & (kFinOut - 1), j = threadIdx.x / kFinOut;
+    const int o = threadIdx.x & (kFinOut - 1), w = threadIdx.x / kFinOut;
     const int e = bid * kFinOut + o;
     const bool is_max = e < NG * GL && (e % GL) >= gram_blocks(RP) * 256;
-    double v = 0.0;
-    if (e < LREC) {
-        const double *src = a.part + e;
+    const double *src = a.part + e;
+#pragma unroll
+    for (int j = w; j < kFinSplit; j += NW) {
+        double v = 0.0;
+        if (e < LREC) {
 #pragma unroll 16
-        for (int b = j; b < a.nblk; b += kFinSplit) {
-            const double x = src[(size_t)b * LREC];
-            v = is_max ? fmax(v, x) : v + x;
+            for (int b = j; b < a.nblk; b += kFinSplit) {
+                const double x = src[(size_t)b * LREC];
+                v = is_max ? fmax(v, x) : v + x;
+            }
         }
+        sh[j][o] = v;
     }
-    sh[j][o] = v;
     __syncthreads();
-    if (j == 0 && e < LREC) {
+    if (w == 0 && e < LREC) {
         double s = sh[0][o];
 #pragma unroll
         for (int q = 1; q < kFinSplit; ++q) s = is_max ? fmax(s, sh[q][o]) : s + sh[q][o];
@@ -768,18 +780,18 @@ __device__ __forceinline__ void finish_sum_body(const FinArgs &a, int bid)
     }
 }
 
-template <int RP, int MODE>
+template <int RP, int MODE, int NT>
 __device__ __forceinline__ void finish_decide_body(const FinArgs &a)
 {
     constexpr int NG = ModeInfo<MODE>::ngram;
-    __shared__ double shd[kFinWaves];
+    __shared__ double shd[kFinThreads / 64];
     DevState *st = a.st;
     int slot[NG];
     if constexpr (ModeInfo<MODE>::sweeps) {
         if (st->done) return;        // set-up launches always run
     }
     fin_slots<RP, MODE>(st, slot);
-    fin_decide<RP, MODE>(a, slot, shd);
+    fin_decide<RP, MODE, NT>(a, slot, shd);
 }
 
 // Decision of the adaptive inner loop after one sweep (one workgroup): the
@@ -827,14 +839,14 @@ __global__ __launch_bounds__(kThreads, 1) void hals_kernel(HalsArgs a)
 template <int RP, int MODE>
 __global__ __launch_bounds__(kFinThreads) void finish_kernel(FinArgs a)
 {
-    finish_sum_body<RP, MODE>(a, blockIdx.x);
+    finish_sum_body<RP, MODE, kFinThreads>(a, blockIdx.x);
 }
 
 // One workgroup: s2, then e(k) and the decision (W sweep) or e(0) (W set-up).
 template <int RP, int MODE>
 __global__ __launch_bounds__(kFinThreads) void decide_kernel(FinArgs a)
 {
-    finish_decide_body<RP, MODE>(a);
+    finish_decide_body<RP, MODE, kFinThreads>(a);
 }
 
 // Grouped forms: one launch over several problems of the same padded rank
@@ -854,26 +866,28 @@ __global__ __launch_bounds__(kThreads, 1) void hals_group_kernel(Group g)
 }
 
 template <int RP, int MODE>
-__global__ __launch_bounds__(kFinThreads) void finish_group_kernel(Group g)
+__global__ __launch_bounds__(kFinGroupThreads) void finish_group_kernel(Group g)
 {
     const int total = group_total(g);
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         int lb, cnt;
         const int p = group_find(g, b, &lb, &cnt);
-        finish_sum_body<RP, MODE>(*reinterpret_cast<const FinArgs *>(g.base + (size_t)p * g.stride), lb);
+        finish_sum_body<RP, MODE, kFinGroupThreads>(
+            *reinterpret_cast<const FinArgs *>(g.base + (size_t)p * g.stride), lb);
         __syncthreads();
     }
 }
 
 // One work block per problem.
 template <int RP, int MODE>
-__global__ __launch_bounds__(kFinThreads) void decide_group_kernel(Group g)
+__global__ __launch_bounds__(kFinGroupThreads) void decide_group_kernel(Group g)
 {
     const int total = group_total(g);
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         int lb, cnt;
         const int p = group_find(g, b, &lb, &cnt);
-        finish_decide_body<RP, MODE>(*reinterpret_cast<const FinArgs *>(g.base + (size_t)p * g.stride));
+        finish_decide_body<RP, MODE, kFinGroupThreads>(
+            *reinterpret_cast<const FinArgs *>(g.base + (size_t)p * g.stride));
         __syncthreads();
     }
 }
@@ -986,11 +1000,11 @@ struct Launch {
     {
         if (w_side) {
             hals_group_kernel<RP, SWEEP_W><<<hblocks, kThreads, 0, s>>>(gh);
-            finish_group_kernel<RP, SWEEP_W><<<fblocks, kFinThreads, 0, s>>>(gf);
-            decide_group_kernel<RP, SWEEP_W><<<dblocks, kFinThreads, 0, s>>>(gd);
+            finish_group_kernel<RP, SWEEP_W><<<fblocks, kFinGroupThreads, 0, s>>>(gf);
+            decide_group_kernel<RP, SWEEP_W><<<dblocks, kFinGroupThreads, 0, s>>>(gd);
         } else {
             hals_group_kernel<RP, SWEEP_H><<<hblocks, kThreads, 0, s>>>(gh);
-            finish_group_kernel<RP, SWEEP_H><<<fblocks, kFinThreads, 0, s>>>(gf);
+            finish_group_kernel<RP, SWEEP_H><<<fblocks, kFinGroupThreads, 0, s>>>(gf);
         }
     }
     // Half-iteration with the adaptive inner loop: `cap` single-sweep launches,
