@@ -140,11 +140,13 @@ size_t layout(Prob &q, char *base)
     b.part_g = (double *)take(sizeof(double) * nblk * nmf::sweep_record(q.rp));
     b.part_d = (double *)take(sizeof(double) * 1024);
     b.st = (DevState *)take(sizeof(DevState));
-    b.trace = (double *)take(sizeof(double) * (q.p.max_iter + 1));
-    b.accepted = (uint8_t *)take((size_t)q.p.max_iter + 1);
-    b.beta_used = (double *)take(sizeof(double) * (q.p.max_iter + 1));
     b.beta_star = (double *)take(sizeof(double) * (q.p.max_iter + 1));
+    // The results, contiguous so that one copy reads them back: W and H
+    // (unpacked into the staging area), trace, beta used, accepted flags.
     b.stage = (float *)take(sizeof(float) * (m + n) * q.r);
+    b.trace = (double *)take(sizeof(double) * (q.p.max_iter + 1));
+    b.beta_used = (double *)take(sizeof(double) * (q.p.max_iter + 1));
+    b.accepted = (uint8_t *)take((size_t)q.p.max_iter + 1);
     b.fsl = (signed char *)take((size_t)std::max(q.ldx, q.ldxt) * 4 * rp);
     b.texp = (int *)take(sizeof(int) * rp);
     q.Xs = take((size_t)q.m_pad * q.ldx * 4);
@@ -227,6 +229,8 @@ struct nmf_batch {
     const DevState **d_states = nullptr; // max_active
     int32_t *d_flags = nullptr;          // 2 x max_active
     int32_t *h_flags = nullptr;          // pinned
+    char *h_res = nullptr;               // pinned read-back area of retiring problems
+    size_t h_res_cap = 0;
     std::vector<Prob *> members[kClasses];
     bool inflight = false;               // a chunk left running by the last step call
 };
@@ -484,32 +488,59 @@ nmf_status retire(nmf_batch *B)
     BHIP(hipGetLastError());
     BHIP(hipMemcpyAsync(B->h_flags, B->d_flags, sizeof(int32_t) * 2 * np, hipMemcpyDeviceToHost, B->s));
     BHIP(hipStreamSynchronize(B->s));
-    std::vector<Prob *> keep;
+    // Every finished problem: W and H unpacked into its staging area, then
+    // one copy of its contiguous results span into the pinned read-back
+    // area; one wait for all of them; then the host copies.
+    std::vector<Prob *> keep, done;
+    std::vector<size_t> at;
+    size_t total = 0;
+    auto span = [](const Prob *q) {
+        return (size_t)(reinterpret_cast<const char *>(q->b.accepted) + q->p.max_iter + 1 -
+                        reinterpret_cast<const char *>(q->b.stage));
+    };
     for (int i = 0; i < np; ++i) {
         Prob *q = B->active[i];
         if (!B->h_flags[2 * i]) {
             keep.push_back(q);
             continue;
         }
-        const int32_t k = B->h_flags[2 * i + 1];
-        q->n_iter = k;
+        q->n_iter = B->h_flags[2 * i + 1];
+        done.push_back(q);
+        at.push_back(total);
+        total += (span(q) + 255) / 256 * 256;
+    }
+    if (done.empty()) return NMF_OK;
+    if (total > B->h_res_cap) {      // grows; no copy into it is in flight here
+        const size_t cap = std::max(total, 2 * B->h_res_cap + (size_t(1) << 20));
+        if (B->h_res) BHIP(hipHostFree(B->h_res));
+        B->h_res = nullptr;
+        B->h_res_cap = 0;
+        BHIP(hipHostMalloc(reinterpret_cast<void **>(&B->h_res), cap));
+        B->h_res_cap = cap;
+    }
+    for (size_t j = 0; j < done.size(); ++j) {
+        Prob *q = done[j];
+        BHIP(nmf::launch_unpack(q->rp, q->m, q->n, q->r, q->b, q->b.stage, q->b.stage + q->m * q->r, B->s));
+        BHIP(hipMemcpyAsync(B->h_res + at[j], q->b.stage, span(q), hipMemcpyDeviceToHost, B->s));
+    }
+    BHIP(hipStreamSynchronize(B->s));
+    for (size_t j = 0; j < done.size(); ++j) {
+        Prob *q = done[j];
+        const char *h = B->h_res + at[j];
+        auto host = [&](const void *dev) {
+            return h + (reinterpret_cast<const char *>(dev) - reinterpret_cast<const char *>(q->b.stage));
+        };
+        const int32_t k = q->n_iter;
         q->W.resize((size_t)q->m * q->r);
         q->H.resize((size_t)q->r * q->n);
         q->trace.resize((size_t)k + 1);
         q->accepted.resize((size_t)k);
         q->beta.resize((size_t)k);
-        BHIP(nmf::launch_unpack(q->rp, q->m, q->n, q->r, q->b, q->b.stage, q->b.stage + q->m * q->r, B->s));
-        BHIP(hipMemcpyAsync(q->W.data(), q->b.stage, sizeof(float) * q->W.size(), hipMemcpyDeviceToHost, B->s));
-        BHIP(hipMemcpyAsync(q->H.data(), q->b.stage + q->m * q->r, sizeof(float) * q->H.size(),
-                            hipMemcpyDeviceToHost, B->s));
-        BHIP(hipMemcpyAsync(q->trace.data(), q->b.trace, sizeof(double) * q->trace.size(),
-                            hipMemcpyDeviceToHost, B->s));
-        if (k > 0) {
-            BHIP(hipMemcpyAsync(q->accepted.data(), q->b.accepted, (size_t)k, hipMemcpyDeviceToHost, B->s));
-            BHIP(hipMemcpyAsync(q->beta.data(), q->b.beta_used, sizeof(double) * k, hipMemcpyDeviceToHost,
-                                B->s));
-        }
-        BHIP(hipStreamSynchronize(B->s));
+        std::memcpy(q->W.data(), h, sizeof(float) * q->W.size());
+        std::memcpy(q->H.data(), h + sizeof(float) * q->W.size(), sizeof(float) * q->H.size());
+        std::memcpy(q->trace.data(), host(q->b.trace), sizeof(double) * q->trace.size());
+        std::memcpy(q->beta.data(), host(q->b.beta_used), sizeof(double) * (size_t)k);
+        std::memcpy(q->accepted.data(), host(q->b.accepted), (size_t)k);
         B->arena.release(q->off, q->bytes);
         std::lock_guard<std::mutex> lk(B->mu);
         q->retired = true;
@@ -790,6 +821,7 @@ void nmf_batch_destroy(nmf_batch *B)
     if (B->d_states) (void)hipFree(B->d_states);
     if (B->d_flags) (void)hipFree(B->d_flags);
     if (B->h_flags) (void)hipHostFree(B->h_flags);
+    if (B->h_res) (void)hipHostFree(B->h_res);
     if (B->pin) (void)hipHostFree(B->pin);
     if (B->s) (void)hipStreamDestroy(B->s);
     for (int c = 0; c < kClasses; ++c)
