@@ -274,7 +274,8 @@ enum nmf_phase {
     NMF_PHASE_SLICE_H = 4,   /* H_w into int8 slices (operand of X H_w^T) */
     NMF_PHASE_PROD_A = 5,    /* A = X H_w^T */
     NMF_PHASE_SWEEP_W = 6,   /* W sweeps, extrapolation, partial Grams, <W_n, A> */
-    NMF_PHASE_FINISH_W = 7,  /* Grams of W_n and W_y', e(k), accept/restart, beta */
+    NMF_PHASE_FINISH_W = 7,  /* Grams of W_n and W_y', then e(k), accept/restart,
+                                beta (two launches) */
     NMF_PHASE_COUNT = 8
 };
 

@@ -510,7 +510,7 @@ nmf_status upload_csr(nmf_ctx *c, const nmf_matrix *X)
     return NMF_OK;
 }
 
-// One outer iteration (eight kernels; four launch steps). With `ev`
+// One outer iteration (nine kernels in eight phases). With `ev`
 // non-null, ev[i] is recorded before kernel i (enum nmf_phase) and
 // ev[NMF_PHASE_COUNT] after the last one.
 nmf_status enqueue_iteration(nmf_ctx *c, hipStream_t s, hipEvent_t *ev = nullptr)
