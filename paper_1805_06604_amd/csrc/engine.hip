@@ -658,6 +658,7 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
     c->b.nsplit_a = c->pa.nsplit;
     c->b.nsplit_c = c->pc.nsplit;
     c->b.lin_f32 = c->prod_kernel == nmf::PK_MFMA_X16;
+    c->b.beta_star_on = (c->p.flags & NMF_FLAG_BETA_STAR) != 0;
     if (p->inner_rule == NMF_INNER_ADAPTIVE) {
         // Sweep caps floor(1 + alpha rho), rho = 1 + (mn + K r) / (R (r + 1)) for
         // R rows updated against K fixed ones (nnz for mn when X is sparse).

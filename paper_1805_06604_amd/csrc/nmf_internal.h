@@ -178,6 +178,7 @@ struct Buffers {
     double *Ct = nullptr;    // nsplit_c x n_pad x RP : partials of X^T W_y
     int nsplit_a = 1, nsplit_c = 1;
     bool lin_f32 = false;    // A and Ct hold FP32 partials (the 16-bit X product)
+    bool beta_star_on = false; // the W sweeps form the beta* diagnostic (its flag set)
     int64_t m_pad = 0, n_pad = 0;
     double *part_g = nullptr;// per-workgroup records of the sweep kernels
     double *part_d = nullptr;// FP64 scratch: reduction partials, the summed <W, A>

@@ -206,7 +206,10 @@ __device__ __forceinline__ double lin_sum(const HalsArgs &a, int64_t off)
 // SWEEP_W (a6 + a7): W_n from W_y by K sweeps with A = X H_w^T and
 //   G = H_w H_w^T; W_y' = W_n + beta (W_n - W); <W_n, A>, Gram(W_n),
 //   Gram(W_y').
-template <int RP, int MODE>
+// BS: the W epilogue holds the beta* diagnostic (computed when its flag is
+// set); the single-problem launches use the instance without it unless the
+// flag was given, which spares that epilogue the diagnostic's registers.
+template <int RP, int MODE, bool BS = true>
 __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
 {
     using MI = ModeInfo<MODE>;
@@ -503,7 +506,7 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
     // <c - x G, dW> and the denominator <dW G, dW>, from the final x (A
     // layout, xa) and dW (moved into A layout through the wave's LDS tile).
     double bs_num = 0.0, bs_den = 0.0;
-    if constexpr (MODE == SWEEP_W) {
+    if constexpr (MODE == SWEEP_W && BS) {
         if (st->flags & kFlagBetaStar) {
             double *xs = s_buf + wave * 16 * XLD;
 #pragma unroll
@@ -830,10 +833,10 @@ static __global__ __launch_bounds__(256) void inner_fin_kernel(InnerFinArgs a)
     }
 }
 
-template <int RP, int MODE>
+template <int RP, int MODE, bool BS = true>
 __global__ __launch_bounds__(kThreads, 1) void hals_kernel(HalsArgs a)
 {
-    hals_body<RP, MODE>(a, blockIdx.x);
+    hals_body<RP, MODE, BS>(a, blockIdx.x);
 }
 
 template <int RP, int MODE>
@@ -972,9 +975,21 @@ struct Launch {
                 h.src_mode = 1;
             }
         }
-        hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
+        sweep_kernel<MODE>(rows, b, h, s);
         if (mid) (void)hipEventRecord(mid, s);
         finish<MODE>(rows, r, b, w_side, s);
+    }
+    // The sweep kernel, on W sides without the beta* code unless asked for.
+    template <int MODE>
+    static void sweep_kernel(int64_t rows, const Buffers &b, const HalsArgs &h, hipStream_t s)
+    {
+        if constexpr (MODE == SWEEP_W) {
+            if (!b.beta_star_on) {
+                hals_kernel<RP, MODE, false><<<hals_blocks(rows), kThreads, 0, s>>>(h);
+                return;
+            }
+        }
+        hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
     }
     // The finish launch of a half-iteration, and the decision launch of the
     // W sides.
@@ -1022,13 +1037,13 @@ struct Launch {
         for (int l = 1; l <= cap; ++l) {
             h.step = f.step = (l == 1) ? 1 : 2;
             h.src_mode = (l == 1) ? 0 : 2;
-            hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
+            sweep_kernel<MODE>(rows, b, h, s);
             inner_fin_kernel<<<1, 256, 0, s>>>(f);
         }
         h.step = 0;
         h.K = 0;
         h.src_mode = 2;
-        hals_kernel<RP, MODE><<<hals_blocks(rows), kThreads, 0, s>>>(h);
+        sweep_kernel<MODE>(rows, b, h, s);
         if (mid) (void)hipEventRecord(mid, s);
         finish<MODE>(rows, r, b, w_side, s);
     }
