@@ -323,7 +323,7 @@ nmf_status alloc_buffers(nmf_ctx *c)
     HIP_TRY(c, dalloc(&b.stage, (size_t)(m + n) * c->r));
     if (c->p.inner_rule == NMF_INNER_ADAPTIVE) {
         HIP_TRY(c, dalloc(&b.x64, (size_t)std::max(m, n) * rp));
-        HIP_TRY(c, dalloc(&b.part_n, (size_t)nblk));
+        HIP_TRY(c, dalloc(&b.part_n, 2 * (size_t)nblk));   // by sweep parity
         HIP_TRY(c, dalloc(&b.sweeps, (size_t)2 * std::max(c->p.max_iter, 1)));
         HIP_TRY(c, hipMemsetAsync(b.sweeps, 0, sizeof(int32_t) * 2 * std::max(c->p.max_iter, 1), c->own));
     }

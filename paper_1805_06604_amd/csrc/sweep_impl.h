@@ -171,13 +171,22 @@ struct HalsArgs {
     // Sweep modes. src_mode: where x starts: 0 the extrapolated slot, 1 the
     // new-iterate slot (filled by the exact NNLS solve, used with K = 0), 2 the
     // FP64 buffer x64 (adaptive inner loop, epilogue with K = 0). step: 0 a
-    // whole half-iteration (K sweeps and the epilogue); 1 / 2 one sweep of the
-    // adaptive loop from the extrapolated slot / from x64, result to x64 and
-    // its squared change to part_n[block] (2: a no-op once the loop stopped).
+    // whole half-iteration (K sweeps and the epilogue); 1 / 2 sweep `sweep`
+    // (1, 2, ...) of the adaptive loop from the extrapolated slot / from x64,
+    // result to x64 and its squared change to part_n (two halves of one
+    // value per block, by the sweep's parity). Sweep l >= 2 first sums the
+    // changes of sweep l - 1 (every workgroup the same way) and takes the
+    // loop's decision: sweep 2 sets the reference change, a later sweep stops
+    // the loop (and returns) once the change is at most delta times it; a
+    // stopped loop's later sweeps return at once. The epilogue after the
+    // loop records the number of sweeps run in sweeps[2 k + side].
     int src_mode;
     int step;
+    int sweep;
+    double delta;
     double *x64;
     double *part_n;
+    int32_t *sweeps;
     // Exact solve: the inverse of the Gram matrix (RP x RP, then a 1 / 0 flag)
     // computed beforehand, or null for an inversion in every workgroup.
     double *ginv;
@@ -244,7 +253,29 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
             src = st->w_y; dst_n = st->w_n; dst_y = st->w_yn; acc_slot = st->w_acc;
         }
         if (a.src_mode == 1) src = dst_n;
-        if (a.step == 2 && st->in_stop) return;
+        if (a.step == 1 && bid == 0 && tid == 0) {
+            st->in_stop = 0;
+            st->in_count = 1;
+        }
+        if (a.step == 2) {
+            if (st->in_stop) return;
+            const int nblk = (int)((a.rows + kRows - 1) / kRows);
+            const double *pn = a.part_n + ((a.sweep - 2) & 1) * (int64_t)nblk;
+            double v = 0.0;
+            for (int i = tid; i < nblk; i += kThreads) v += pn[i];
+            v = block_sum(v, &s_s1[0][0]);
+            const double d = sqrt(v);                 // change of sweep sweep - 1
+            if (a.sweep > 2 && d <= a.delta * st->in_eps0) {
+                if (bid == 0 && tid == 0) st->in_stop = 1;
+                return;
+            }
+            if (bid == 0 && tid == 0) {
+                if (a.sweep == 2) st->in_eps0 = d;
+                st->in_count = a.sweep;
+            }
+        }
+        if (a.step == 0 && a.src_mode == 2 && bid == 0 && tid == 0)
+            a.sweeps[2 * st->k + (MODE == SWEEP_W ? 1 : 0)] = st->in_count;
     }
     const float *xsrc = a.fac + src * a.slot_stride;
     const double *x64 = (MI::sweeps && a.src_mode == 2) ? a.x64 : nullptr;
@@ -450,7 +481,8 @@ __device__ __forceinline__ void hals_body(const HalsArgs &a, int bid)
                 }
             }
             d2 = block_sum(d2, &s_s1[0][0]);
-            if (tid == 0) a.part_n[bid] = d2;
+            if (tid == 0)
+                a.part_n[((a.sweep - 1) & 1) * ((a.rows + kRows - 1) / kRows) + bid] = d2;
             return;
         }
     }
@@ -797,42 +829,6 @@ __device__ __forceinline__ void finish_decide_body(const FinArgs &a)
     fin_decide<RP, MODE, NT>(a, slot, shd);
 }
 
-// Decision of the adaptive inner loop after one sweep (one workgroup): the
-// squared changes of the workgroups summed in a fixed order; the first sweep
-// sets ||x^(1) - x^(0)||_F, a later one stops the loop once its change is at
-// most delta times that. The count of sweeps run goes to sweeps[2 k + side].
-struct InnerFinArgs {
-    const double *part_n;
-    int nblk;
-    int step;              // 1 first sweep, 2 later sweep
-    int side;              // 0 H, 1 W
-    double delta;
-    DevState *st;
-    int32_t *sweeps;
-};
-
-static __global__ __launch_bounds__(256) void inner_fin_kernel(InnerFinArgs a)
-{
-    __shared__ double sh[4];
-    DevState *st = a.st;
-    if (st->done || (a.step == 2 && st->in_stop)) return;
-    double v = 0.0;
-    for (int i = threadIdx.x; i < a.nblk; i += 256) v += a.part_n[i];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) {
-        const double d = sqrt(v);
-        if (a.step == 1) {
-            st->in_eps0 = d;
-            st->in_stop = 0;
-            st->in_count = 1;
-        } else {
-            st->in_count += 1;
-            if (d <= a.delta * st->in_eps0) st->in_stop = 1;
-        }
-        a.sweeps[2 * st->k + a.side] = st->in_count;
-    }
-}
-
 template <int RP, int MODE, bool BS = true>
 __global__ __launch_bounds__(kThreads, 1) void hals_kernel(HalsArgs a)
 {
@@ -1022,10 +1018,10 @@ struct Launch {
             finish_group_kernel<RP, SWEEP_H><<<fblocks, kFinGroupThreads, 0, s>>>(gf);
         }
     }
-    // Half-iteration with the adaptive inner loop: `cap` single-sweep launches,
-    // each followed by its one-workgroup decision (launches after the stop are
-    // no-ops), then the sweep kernel with no sweeps from the FP64 buffer for
-    // the epilogue, and the finish kernel.
+    // Half-iteration with the adaptive inner loop: `cap` single-sweep launches
+    // (each takes the loop's decision on the previous sweep; launches after
+    // the stop are no-ops), then the sweep kernel with no sweeps from the FP64
+    // buffer for the epilogue, and the finish kernel.
     template <int MODE>
     static void adaptive(int64_t rows, int r, int cap, double delta, const Buffers &b, bool w_side,
                          hipStream_t s, hipEvent_t mid)
@@ -1033,12 +1029,13 @@ struct Launch {
         HalsArgs h = hals_args(RP, rows, r, 1, b, w_side);
         h.x64 = b.x64;
         h.part_n = b.part_n;
-        InnerFinArgs f{b.part_n, hals_blocks(rows), 1, w_side ? 1 : 0, delta, b.st, b.sweeps};
+        h.sweeps = b.sweeps;
+        h.delta = delta;
         for (int l = 1; l <= cap; ++l) {
-            h.step = f.step = (l == 1) ? 1 : 2;
+            h.step = (l == 1) ? 1 : 2;
+            h.sweep = l;
             h.src_mode = (l == 1) ? 0 : 2;
             sweep_kernel<MODE>(rows, b, h, s);
-            inner_fin_kernel<<<1, 256, 0, s>>>(f);
         }
         h.step = 0;
         h.K = 0;
