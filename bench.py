@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=2048,
                     help="m = n of the oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--cpu-serve-sample", type=int, default=4,
+                    help="serving requests the oracle solves to the end (0: none)")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--cpu-full", type=int, default=1,
                     help="1: also time one oracle iteration on the full benchmark problem")
@@ -187,6 +189,30 @@ def cpu_baseline(args, p_full):
             cfg[name] = {"iters_per_s": iters / t, "iters": iters, "seconds": t}
         out["workloads"] = cfg
     return out
+
+
+def cpu_serving(args, probs):
+    """The oracle (single thread, error by Remark 1) on a seeded random sample
+    of the serving stream's requests, each solved to the end exactly as the
+    batch solves it (<= 200 iterations or the tol rule)."""
+    import oracle
+    rng = np.random.default_rng(12345)
+    idx = sorted(rng.choice(len(probs), size=min(args.cpu_serve_sample, len(probs)),
+                            replace=False).tolist())
+    t0 = time.perf_counter()
+    iters = []
+    for i in idx:
+        p = probs[i]
+        o = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=200, tol=1e-6, hp=3, beta0=0.5,
+                         gamma=1.01, gamma_bar=1.005, eta=1.5, inner_k=args.inner_k,
+                         flags=oracle.ERR_REMARK1)
+        iters.append(o["n_iter"])
+    t = time.perf_counter() - t0
+    return {"solves_per_s": len(idx) / t, "requests": len(idx), "seconds": t,
+            "mean_iters": float(np.mean(iters)),
+            "mean_mn": float(np.mean([probs[i].X.shape[0] * probs[i].X.shape[1] for i in idx])),
+            "sample": (f"{len(idx)} requests drawn at random (seed 12345) from the "
+                       f"{len(probs)}-request stream, each solved to the end by the oracle")}
 
 
 FP64_VECTOR_PEAK_TFS = 78.6
@@ -568,6 +594,8 @@ def main():
         if args.serve_qps_low > 0:
             out["serving_below_saturation"] = serving(args, P, S, args.serve_qps_low, 0, probs,
                                                       t_gen)
+        if cpu is not None and args.cpu_serve_sample > 0:
+            cpu["serving"] = cpu_serving(args, probs)
         del probs
     if cpu is not None:
         out["cpu_baseline"] = cpu
