@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=2048,
                     help="m = n of the oracle sample (0 disables the CPU baseline)")
-    ap.add_argument("--cpu-serve-sample", type=int, default=4,
+    ap.add_argument("--cpu-serve-sample", type=int, default=16,
                     help="serving requests the oracle solves to the end (0: none)")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--cpu-full", type=int, default=1,
