@@ -86,11 +86,12 @@ typedef enum { NMF_INNER_FIXED = 0, NMF_INNER_EXACT = 1, NMF_INNER_ADAPTIVE = 2 
  *                factor is sliced per column the same way, and the slice
  *                products are summed exactly in int32: products to about
  *                2^-27 of the row and column maxima, no rounding over K.
- *   MFMA_FAST  : BF16 matrix cores, operands carried to 16 significant bits,
- *                sums in FP32 within a K-chunk. X keeps its x_dtype storage
- *                (2 bytes per entry for BF16 and FP16 X, which the product
- *                streams in its own fragment order; the factor is split into
- *                two BF16 parts once per product). */
+ *   MFMA_FAST  : 16-bit matrix cores of X's type (BF16 or FP16), X as
+ *                stored and the factor split into two parts of that type
+ *                once per product (FP16 parts scaled per column by a power
+ *                of two), sums in FP32 within a K-chunk. X keeps its x_dtype
+ *                storage (2 bytes per entry, which the product streams in its
+ *                own fragment order). */
 typedef enum {
     NMF_PROD_AUTO = 0,
     NMF_PROD_VALU = 1,

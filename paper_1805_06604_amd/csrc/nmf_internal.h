@@ -151,7 +151,7 @@ struct ProdArgs {
     const double *gram_base;
     int64_t gram_slot_stride;
     signed char *Fsl;       // the factor in int8 slices: (ld / 64) x 4 x RP x 64, or
-                            // (16-bit X) in two BF16 parts: (ld / 64) x 2 x 2 x RP x 64 B
+                            // (16-bit X) in two parts of X's type: (ld / 64) x 2 x 2 x RP x 64 B
     int *texp;              // its column scale exponents (RP)
     // Sparse kernel only: the CSR operand (host pointer to its plan).
     const CsrPlan *csr;
@@ -160,7 +160,7 @@ struct ProdArgs {
 // Product kernels: VALU FP64 FMA over the stored values (products exact, sums
 // in FP64); the exact-integer matrix-core product (X and the factor in int8
 // slices, int32 sums); the sparse product; and the 16-bit X product on the
-// BF16 matrix cores (X in fragment order, the factor split into two BF16
+// 16-bit matrix cores (X in fragment order, the factor split into two 16-bit
 // parts once per product, FP32 sums within a K-chunk).
 enum ProdKernel { PK_VALU = 0, PK_MFMA_I8 = 3, PK_CSR = 4, PK_MFMA_X16 = 5 };
 

@@ -1,14 +1,16 @@
-// X-streaming products for X stored in 16 bits (BF16 or FP16) on the BF16
+// X-streaming products for X stored in 16 bits (BF16 or FP16) on the 16-bit
 // matrix cores (arXiv 1805.06604: the W^T X and X H^T terms of the HALS
 // updates, section 1 and Remark 1).
 //
-// Precision. The factor is split once per product into two BF16 parts,
-// f = f0 + f1 + (at most 2^-16 |f|), round to nearest at each step. BF16 X is
-// one part; FP16 X is split on the fly into two (exact). The part pairs of
-// relative weight >= 2^-8 are kept (x0 f0, x0 f1, and x1 f0 for FP16) and
-// accumulated in FP32 on v_mfma_f32_16x16x32_bf16 within the K-chunk; the
-// K-chunk partials are written in FP32 and summed in FP64 by the sweep
-// kernels.
+// Precision. The factor is split once per product into two parts of the X
+// type, f = f0 + f1 + (a rounding residue), round to nearest at each step:
+// for BF16 X two BF16 parts (residue at most 2^-16 |f|); for FP16 X two FP16
+// parts of f 2^t_k, with a power of two per column from the column maximum
+// (the largest scaled value below 2^15, residue at most 2^-22 of it), taken
+// out again when the sums are stored. X feeds the matrix cores as stored:
+// two products per k-step (x f0 and x f1), accumulated in FP32 on
+// v_mfma_f32_16x16x32_bf16 / _f16 within the K-chunk; the K-chunk partials
+// are written in FP32 and summed in FP64 by the sweep kernels.
 //
 // Z layout (fragment order). The 16-bit copy of Z (X or the resident X^T) is
 // stored per 16-row block and 64-column tile as 2 k-steps x 64 lanes x 16
@@ -48,7 +50,7 @@ constexpr int kWM = 16 * kBPW;          // rows per wave
 constexpr int kBM = kWaves * kWM;       // rows per workgroup
 static_assert(kBM == kX16Rows, "row padding of the 16-bit path");
 constexpr int kKT = 64;                 // K per tile (two MFMA k-steps)
-constexpr int kFP = 2;                  // BF16 parts of the factor
+constexpr int kFP = 2;                  // parts of the factor
 constexpr int kTPS = 1;                 // tiles per step (one barrier per step)
 constexpr int kDepth = 3;               // steps in flight ahead of the multiply
 constexpr int kBufs = kDepth + 1;       // register buffers = LDS stages = K-loop unroll
@@ -61,12 +63,49 @@ __host__ __device__ constexpr int fgroup(int c, int g) { return g ^ ((c >> 2) & 
 // s_waitcnt immediate: vmcnt(n) (bits 3:0 and 15:14), lgkmcnt(0), no expcnt wait.
 __host__ __device__ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0070; }
 
+// Operand vectors of 8 16-bit values and the matrix-core product of the X
+// type.
+template <typename XT> struct Ops16;
+template <> struct Ops16<__hip_bfloat16> {
+    typedef bf16x8 vec;
+    typedef __bf16 elem;
+    static constexpr bool scaled = false;
+    __device__ static floatx4 mfma(vec x, vec f, floatx4 acc)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, f, acc, 0, 0, 0);
+    }
+};
+template <> struct Ops16<__half> {
+    typedef half8 vec;
+    typedef _Float16 elem;
+    static constexpr bool scaled = true;
+    __device__ static floatx4 mfma(vec x, vec f, floatx4 acc)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, f, acc, 0, 0, 0);
+    }
+};
+
+// Column scale exponent t of the FP16 factor parts: |f| 2^t < 2^15 for
+// |f| <= amax (0 for amax == 0).
+__host__ __device__ inline int half_exponent(double amax)
+{
+    if (!(amax > 0.0)) return 0;
+    int e;
+    frexp(amax, &e);            // amax = m 2^e, m in [0.5, 1)
+    return 15 - e;
+}
+
 // Splits one 64-row tile of the factor F (K x RP, FP32) per workgroup into
-// Fsp[tile][k-step][part][column][4 groups of 16 B] (BF16, B-operand order,
-// groups swizzled by fgroup, zero past K).
-template <int RP>
+// Fsp[tile][k-step][part][column][4 groups of 16 B] (parts of the X type in
+// B-operand order, groups swizzled by fgroup, zero past K); for FP16 parts
+// the columns are scaled by 2^t_k first (t_k from the column maxima in the
+// Gram buffer's tail; block 0 also stores t_k).
+template <int RP, typename XT>
 __device__ __forceinline__ void split_body(const ProdArgs &a, int bid)
 {
+    typedef typename Ops16<XT>::vec vec;
+    typedef typename Ops16<XT>::elem elem;
+    __shared__ int s_texp[RP];
     const DevState *st = a.st;
     int slot = 0;
     if (a.sel != SEL_SLOT0) {
@@ -74,6 +113,15 @@ __device__ __forceinline__ void split_body(const ProdArgs &a, int bid)
         slot = (a.sel == SEL_W_Y) ? st->w_y : (st->hp == 1 ? st->h_n : st->h_yn);
     }
     const float *__restrict__ F = a.F_base + slot * a.slot_stride;
+    if constexpr (Ops16<XT>::scaled) {
+        const double *colmax = (a.sel == SEL_W_Y ? a.gram_base + (size_t)st->w_y * a.gram_slot_stride
+                                                 : a.gram_base) + RP * RP + RP;
+        if (threadIdx.x < RP) {
+            s_texp[threadIdx.x] = half_exponent(colmax[threadIdx.x]);
+            if (bid == 0) a.texp[threadIdx.x] = s_texp[threadIdx.x];
+        }
+        __syncthreads();
+    }
     const int64_t tile = bid;
     signed char *out = a.Fsl + tile * (2 * kFP * RP * 64);
     // One item per (k-step s, column c, group g): 8 rows, both parts.
@@ -84,42 +132,19 @@ __device__ __forceinline__ void split_body(const ProdArgs &a, int bid)
         for (int e = 0; e < 8; ++e) {
             const int64_t k = tile * kKT + 32 * s + 8 * g + e;
             f[e] = (k < a.K) ? F[k * RP + c] : 0.0f;
+            if constexpr (Ops16<XT>::scaled) f[e] = ldexpf(f[e], s_texp[c]);   // exact
         }
-        bf16x8 p0, p1;
+        vec p0, p1;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const __bf16 h = (__bf16)f[e];
+            const elem h = (elem)f[e];
             p0[e] = h;
-            p1[e] = (__bf16)(f[e] - (float)h);
+            p1[e] = (elem)(f[e] - (float)h);
         }
-        *reinterpret_cast<bf16x8 *>(out + ((s * kFP + 0) * RP + c) * 64 + fgroup(c, g) * 16) = p0;
-        *reinterpret_cast<bf16x8 *>(out + ((s * kFP + 1) * RP + c) * 64 + fgroup(c, g) * 16) = p1;
+        *reinterpret_cast<vec *>(out + ((s * kFP + 0) * RP + c) * 64 + fgroup(c, g) * 16) = p0;
+        *reinterpret_cast<vec *>(out + ((s * kFP + 1) * RP + c) * 64 + fgroup(c, g) * 16) = p1;
     }
 }
-
-// The MFMA A operand(s) of 8 X values held as 16 raw bytes.
-template <typename XT> struct XOps;
-template <> struct XOps<__hip_bfloat16> {
-    static constexpr int n = 1;
-    __device__ static void get(const int32x4 &raw, bf16x8 (&x)[1])
-    {
-        x[0] = __builtin_bit_cast(bf16x8, raw);
-    }
-};
-template <> struct XOps<__half> {
-    static constexpr int n = 2;
-    __device__ static void get(const int32x4 &raw, bf16x8 (&x)[2])
-    {
-        const half8 h = __builtin_bit_cast(half8, raw);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float f = (float)h[e];
-            const __bf16 a = (__bf16)f;
-            x[0][e] = a;
-            x[1][e] = (__bf16)(f - (float)a);   // exact: 11 significant bits in all
-        }
-    }
-};
 
 template <int RP, typename XT>
 __device__ __forceinline__ void prod_body(const ProdArgs &args, int bid)
@@ -127,8 +152,8 @@ __device__ __forceinline__ void prod_body(const ProdArgs &args, int bid)
     // A private copy: the grouped form would otherwise re-read the argument
     // record after every direct-to-LDS load.
     const ProdArgs a = args;
+    typedef typename Ops16<XT>::vec vec;
     constexpr int NCB = RP / 16;
-    constexpr int NX = XOps<XT>::n;
     constexpr int FT = 2 * kFP * RP * 64;             // split factor tile bytes (RP KB)
     constexpr int FTK = FT / 1024;
     constexpr int SFK = kTPS * FTK;                   // factor KB per step
@@ -212,30 +237,24 @@ __device__ __forceinline__ void prod_body(const ProdArgs &args, int bid)
                     const int64_t t = t0 + kTPS * j + h;
                     if (j >= 0 && t < t1) {                     // (uniform)
                         const signed char *ft = ring[u] + h * FT;
-                        bf16x8 xs[kBPW][2][NX];
-#pragma unroll
-                        for (int b = 0; b < kBPW; ++b)
-#pragma unroll
-                            for (int s = 0; s < 2; ++s) XOps<XT>::get(z[u][h][b][s], xs[b][s]);
 #pragma unroll
                         for (int s = 0; s < 2; ++s) {
-                            bf16x8 bp[NCB][kFP];
+                            vec bp[NCB][kFP];
 #pragma unroll
                             for (int c = 0; c < NCB; ++c)
 #pragma unroll
                                 for (int p = 0; p < kFP; ++p)
-                                    bp[c][p] = *reinterpret_cast<const bf16x8 *>(
+                                    bp[c][p] = *reinterpret_cast<const vec *>(
                                         ft + ((s * kFP + p) * RP + 16 * c) * 64 + boff);
 #pragma unroll
-                            for (int i = 0; i < NX; ++i)
+                            for (int p = 0; p < kFP; ++p)
 #pragma unroll
-                                for (int p = 0; p + i <= 1; ++p)
+                                for (int b = 0; b < kBPW; ++b)
 #pragma unroll
-                                    for (int b = 0; b < kBPW; ++b)
-#pragma unroll
-                                        for (int c = 0; c < NCB; ++c)
-                                            acc[b][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                                xs[b][s][i], bp[c][p], acc[b][c], 0, 0, 0);
+                                    for (int c = 0; c < NCB; ++c)
+                                        acc[b][c] = Ops16<XT>::mfma(
+                                            __builtin_bit_cast(vec, z[u][h][b][s]), bp[c][p],
+                                            acc[b][c]);
                         }
                     }
                 }
@@ -246,21 +265,29 @@ __device__ __forceinline__ void prod_body(const ProdArgs &args, int bid)
 
     // D layout: lane holds column lr of each block, rows 4g..4g+3. The
     // K-chunk's FP32 sums are stored as they are (FP32 partials; the sweep
-    // kernels add them in FP64).
+    // kernels add them in FP64), FP16 ones scaled back by 2^-t_k (exact).
     float *Y = reinterpret_cast<float *>(a.Y) + (size_t)kc * a.rows_pad * RP;
+    int te[NCB] = {};
+    if constexpr (Ops16<XT>::scaled) {
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) te[c] = a.texp[c * 16 + lr];
+    }
 #pragma unroll
     for (int b = 0; b < kBPW; ++b)
 #pragma unroll
         for (int c = 0; c < NCB; ++c)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                Y[(row0 + 16 * b + 4 * g + i) * RP + c * 16 + lr] = acc[b][c][i];
+            for (int i = 0; i < 4; ++i) {
+                float v = acc[b][c][i];
+                if constexpr (Ops16<XT>::scaled) v = ldexpf(v, -te[c]);
+                Y[(row0 + 16 * b + 4 * g + i) * RP + c * 16 + lr] = v;
+            }
 }
 
-template <int RP>
+template <int RP, typename XT>
 __global__ __launch_bounds__(256) void split_factor_kernel(ProdArgs a)
 {
-    split_body<RP>(a, blockIdx.x);
+    split_body<RP, XT>(a, blockIdx.x);
 }
 
 template <int RP, typename XT>
@@ -272,7 +299,7 @@ __global__ __launch_bounds__(kWaves * 64, 1) void prod_x16_kernel(ProdArgs a)
 template <int RP, typename XT>
 void launch(const ProdArgs &a, hipStream_t s, hipEvent_t mid)
 {
-    split_factor_kernel<RP><<<(unsigned)(a.ld / kKT), 256, 0, s>>>(a);
+    split_factor_kernel<RP, XT><<<(unsigned)(a.ld / kKT), 256, 0, s>>>(a);
     if (mid) (void)hipEventRecord(mid, s);
     const int64_t blocks = (a.rows_pad / kBM) * a.nsplit;
     prod_x16_kernel<RP, XT><<<(unsigned)blocks, kWaves * 64, 0, s>>>(a);

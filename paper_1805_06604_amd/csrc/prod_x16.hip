@@ -1,4 +1,4 @@
-// 16-bit X products on the BF16 matrix cores (one instance per padded rank and
+// 16-bit X products on the 16-bit matrix cores (one instance per padded rank and
 // storage type) and the one-time copy of X and X^T into their fragment order.
 #include "prod_x16.h"
 

@@ -103,7 +103,7 @@ def test_imagelike_10000x2000_r49(exact):
 
 @pytest.mark.parametrize("xd", ["BF16", "F16"])
 def test_planted_16384_r64_16bit_x(planted, xd):
-    """The benchmark configuration with X stored in 16 bits (BF16 matrix-core
+    """The benchmark configuration with X stored in 16 bits (16-bit matrix-core
     products): after 30 iterations the final error, evaluated in FP64 against
     the FP32 X, is within 1e-3 absolute of the FP32 path's at the same
     iteration (the FP32 path being the one checked against the oracle

@@ -5,7 +5,7 @@ sizes the oracle finishes in about a minute:
     2048 x 2048, r = 64, with the benchmark's parameters (hp 3, beta0 0.5,
     gamma 1.01, gamma_bar 1.005, eta 1.5, K = 10): the exact-integer
     product path by the full parity protocol, and X stored in BF16 and FP16
-    (BF16 matrix-core products) by the final error against the FP32 X,
+    (16-bit matrix-core products) by the final error against the FP32 X,
     within 1e-3 absolute of the oracle's on the FP32 X;
   * the image-like 10000 x 2000, r = 49 set at its full size (the stand-in
     for the face-image sets), by the full parity protocol.

@@ -1,4 +1,4 @@
-"""X stored in 16 bits (BF16, FP16) with the BF16 matrix-core product: the
+"""X stored in 16 bits (BF16, FP16) with the 16-bit matrix-core product: the
 final error against the FP64 oracle on the FP32 X at the stated accuracy
 (1e-3 absolute), over every padded rank class and ragged shapes (partial
 256-row workgroups, partial K-chunks, a single row or column); and the
@@ -56,9 +56,10 @@ def test_final_error_ragged(xd, m, n, r):
 
 @pytest.mark.parametrize("xd", ["BF16", "F16"])
 def test_product_against_fp64_products(xd):
-    """Same 16-bit X, products on the BF16 matrix cores (factor carried to 16
-    significant bits, FP32 sums) against exact FP64 products: over the first
-    iterations the traces agree to within the product's accuracy."""
+    """Same 16-bit X, products on the 16-bit matrix cores (factor carried to 16
+    significant bits for BF16, 22 for FP16; FP32 sums) against exact FP64
+    products: over the first iterations the traces agree to within the
+    product's accuracy."""
     p = S.planted(8, m=900, n=700, r=40)
     kw = dict(x_dtype=P.XDtype[xd], **ALG)
     a = _run(p, 8, prod=P.Prod.MFMA_FAST, **kw)
