@@ -231,6 +231,8 @@ struct nmf_batch {
     // above, so they stay valid while the active set changes).
     hipGraphExec_t exec_one[kClasses] = {};
     hipGraphExec_t exec_chunk[kClasses] = {};
+    bool need_exact[kClasses] = {};      // a member of the class runs exact NNLS solves
+    bool cap_exact[kClasses] = {};       // the class's graphs hold the exact launches
     const DevState **d_states = nullptr; // max_active
     int32_t *d_flags = nullptr;          // 2 x max_active
     int32_t *h_flags = nullptr;          // pinned
@@ -366,6 +368,7 @@ nmf_status rebuild(nmf_batch *B)
     for (int c = 0; c < kClasses; ++c) {
         const int rp = 16 * (c + 1);
         auto &mem = B->members[c];
+        B->need_exact[c] = false;
         for (size_t i = 0; i < mem.size(); ++i) {
             Prob &q = *mem[i];
             Entry &E = ent[(size_t)c * cap + i];
@@ -374,6 +377,7 @@ nmf_status rebuild(nmf_batch *B)
             E.hh = nmf::sweep::hals_args(rp, q.n, q.r, q.p.inner_k, q.b, false);
             E.hw = nmf::sweep::hals_args(rp, q.m, q.r, q.p.inner_k, q.b, true);
             const bool exact = q.p.inner_rule == NMF_INNER_EXACT;
+            B->need_exact[c] = B->need_exact[c] || exact;
             if (exact) {        // the exact solve fills the new slot; no sweeps after it
                 E.hh.K = E.hw.K = 0;
                 E.hh.src_mode = E.hw.src_mode = 1;
@@ -404,6 +408,16 @@ nmf_status rebuild(nmf_batch *B)
         BHIP(hipMemcpyAsync(B->d_states, sts.data(), sizeof(DevState *) * sts.size(),
                             hipMemcpyHostToDevice, B->s));
     BHIP(hipStreamSynchronize(B->s));
+    // A class's graphs hold the exact launches only while a member needs
+    // them; they are captured again when that changes (the class streams are
+    // idle here).
+    for (int c = 0; c < kClasses; ++c) {
+        if (!B->exec_one[c] || B->cap_exact[c] == B->need_exact[c]) continue;
+        BHIP(hipGraphExecDestroy(B->exec_one[c]));
+        B->exec_one[c] = nullptr;
+        if (B->exec_chunk[c]) BHIP(hipGraphExecDestroy(B->exec_chunk[c]));
+        B->exec_chunk[c] = nullptr;
+    }
     B->dirty = false;
     return NMF_OK;
 }
@@ -423,18 +437,21 @@ Group group_of(nmf_batch *B, int c, int kind, size_t member_offset)
 constexpr int kGrid[kKinds] = {1024, 256, 512, 1024, 1024, 256, 512, 1024, 512, 512, 512};
 
 // One batch iteration of padded-rank class c on stream cs: both products,
-// the exact solves (a no-op without E-ANLS problems) and both sweep steps.
+// the exact solves (when a member of the class is an E-ANLS problem) and both
+// sweep steps.
 nmf_status enqueue_class_iteration(nmf_batch *B, int c, hipStream_t cs)
 {
     const int rp = 16 * (c + 1);
     BHIP(nmf::i8::launch_group(rp, group_of(B, c, 0, offsetof(Entry, pc)), kGrid[0],
                                group_of(B, c, 1, offsetof(Entry, pc)), kGrid[1], cs));
-    BHIP(nmf::launch_group_exact(rp, false, group_of(B, c, 8, offsetof(Entry, hh)), kGrid[8], cs));
+    if (B->need_exact[c])
+        BHIP(nmf::launch_group_exact(rp, false, group_of(B, c, 8, offsetof(Entry, hh)), kGrid[8], cs));
     BHIP(nmf::launch_group_sweep(rp, false, group_of(B, c, 2, offsetof(Entry, hh)), kGrid[2],
                                  group_of(B, c, 3, offsetof(Entry, fh)), kGrid[3], Group{}, 0, cs));
     BHIP(nmf::i8::launch_group(rp, group_of(B, c, 4, offsetof(Entry, pa)), kGrid[4],
                                group_of(B, c, 5, offsetof(Entry, pa)), kGrid[5], cs));
-    BHIP(nmf::launch_group_exact(rp, true, group_of(B, c, 9, offsetof(Entry, hw)), kGrid[9], cs));
+    if (B->need_exact[c])
+        BHIP(nmf::launch_group_exact(rp, true, group_of(B, c, 9, offsetof(Entry, hw)), kGrid[9], cs));
     BHIP(nmf::launch_group_sweep(rp, true, group_of(B, c, 6, offsetof(Entry, hw)), kGrid[6],
                                  group_of(B, c, 7, offsetof(Entry, fw)), kGrid[7],
                                  group_of(B, c, 10, offsetof(Entry, fw)), kGrid[10], cs));
@@ -469,6 +486,7 @@ nmf_status run_iterations(nmf_batch *B, int iters)
     for (int c = 0; c < kClasses; ++c) {
         if (B->members[c].empty()) continue;
         if (!B->exec_one[c]) {
+            B->cap_exact[c] = B->need_exact[c];
             nmf_status st = capture_class(B, c, 1, &B->exec_one[c]);
             if (st == NMF_OK && B->bp.check_every > 1)
                 st = capture_class(B, c, B->bp.check_every, &B->exec_chunk[c]);

@@ -125,3 +125,45 @@ def test_mixed_rules_in_one_batch():
         print(f"problem {i} rule {'EXACT' if i % 2 else 'FIXED'}", flush=True)
         compare_to_oracle(p, out[i], 40, oracle_flags=oracle.EXACT_NNLS if i % 2 else 0,
                           inner_k=10, **v.params())
+
+
+def test_class_gains_and_loses_exact_members():
+    """One padded rank, at most two problems on the GPU at a time, E-A-HALS
+    and E-ANLS problems of different lengths: the class's graphs drop the
+    exact launches when its last E-ANLS problem retires and take them again
+    when the next one is admitted. Each result equals the same problem run
+    alone in a batch, bit for bit, and matches the oracle."""
+    import oracle
+    probs = [S.fullrank(10 + s, m=170, n=140, r=12) for s in range(5)]
+    v = G.Variant(1, 0.5, 1.5, 1.1, 1.05)
+    spec = [(False, 30), (True, 10), (False, 20), (False, 20), (True, 20)]
+    print("admission order: fixed 30, exact 10, fixed 20, fixed 20, exact 20; "
+          "max_active 2", flush=True)
+
+    def kw(i):
+        exact, n_it = spec[i]
+        return dict(max_iter=n_it, inner_k=10, inner_rule=P.Inner.EXACT if exact else P.Inner.FIXED,
+                    **v.params())
+
+    def run(idx, max_active):
+        out = {}
+        with P.Batch(1 << 28, max_active=max_active, check_every=5) as B:
+            t = {i: B.submit(probs[i].X, probs[i].r, probs[i].W0, probs[i].H0, **kw(i)) for i in idx}
+            while len(out) < len(t):
+                B.step(5)
+                for i, ti in t.items():
+                    if i not in out:
+                        g = B.result(ti)
+                        if g is not None:
+                            out[i] = g
+        return out
+
+    mixed = run(range(5), 2)
+    for i, p in enumerate(probs):
+        exact, n_it = spec[i]
+        print(f"problem {i} rule {'EXACT' if exact else 'FIXED'} iterations {n_it}", flush=True)
+        alone = run([i], 1)[i]
+        assert np.array_equal(alone.trace, mixed[i].trace)
+        assert np.array_equal(alone.W, mixed[i].W) and np.array_equal(alone.H, mixed[i].H)
+        compare_to_oracle(p, mixed[i], n_it, oracle_flags=oracle.EXACT_NNLS if exact else 0,
+                          inner_k=10, **v.params())
