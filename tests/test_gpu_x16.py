@@ -76,3 +76,29 @@ def test_bf16_runs_are_bitwise_deterministic():
     np.testing.assert_array_equal(a.trace, b.trace)
     np.testing.assert_array_equal(a.W, b.W)
     np.testing.assert_array_equal(a.H, b.H)
+
+
+@pytest.mark.parametrize("xd", ["BF16", "F16"])
+def test_factor_columns_of_very_different_scales(xd):
+    """Factor columns scaled by 2^-24 .. 2^12 (and the rows of H0 by the
+    inverse, so that W0 H0 is unchanged), X already representable in the
+    16-bit type: after one outer iteration every row of H and every column of
+    W matches the FP64 oracle on the same X to 1e-3 relative. FP16 factor
+    parts without their per-column scale would underflow to zero on the small
+    columns and overflow on the large rows."""
+    p = S.planted(9, m=300, n=260, r=16)
+    Xq = quantized(p.X, xd)
+    s = np.exp2(np.linspace(-24, 12, p.r)).astype(np.float32)
+    W0 = (p.W0 * s[None, :]).astype(np.float32)
+    H0 = (p.H0 / s[:, None]).astype(np.float32)
+    print(f"case {xd} m={p.m} n={p.n} r={p.r} column scales 2^-24..2^12", flush=True)
+    with P.Solver(Xq, p.r, max_iter=1, x_dtype=P.XDtype[xd], prod=P.Prod.MFMA_FAST, **ALG) as sv:
+        g = sv.solve(W0, H0)
+    ref = oracle.solve(Xq, p.r, W0, H0, max_iter=1, **ALG)
+    assert np.array_equal(g.accepted, ref["accepted"])
+    dh = np.linalg.norm(g.H - ref["H"], axis=1) / np.linalg.norm(ref["H"], axis=1)
+    dw = np.linalg.norm(g.W - ref["W"], axis=0) / np.linalg.norm(ref["W"], axis=0)
+    print(f"  max relative deviation: rows of H {dh.max():.2e}, columns of W {dw.max():.2e}",
+          flush=True)
+    assert np.all(np.isfinite(g.W)) and np.all(np.isfinite(g.H))
+    assert dh.max() < 1e-3 and dw.max() < 1e-3
