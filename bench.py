@@ -268,31 +268,50 @@ def eanls(args, P, p, stream, torch):
                          "flops_per_iteration": flops, "ms_per_iteration": solve_ms}}
 
 
-def adaptive(args, P, p, stream, torch):
+def device_cost_ratios(phases, K):
+    """Cost ratios of the adaptive loop's caps measured on the device: 1 +
+    the time of one side's X pass (slicing the fixed factor and the product)
+    over that of one of its sweeps (the sweep kernel's time over its K
+    sweeps, prologue and epilogue included), from the per-kernel times of
+    the fixed-K headline run."""
+    rho_h = 1.0 + (phases["slice_w"] + phases["prod_ct"]) / (phases["sweep_h"] / K)
+    rho_w = 1.0 + (phases["slice_h"] + phases["prod_a"]) / (phases["sweep_w"] / K)
+    return rho_h, rho_w
+
+
+def adaptive(args, P, p, stream, torch, rho=None, steps=None):
     """E-A-HALS with the adaptive inner loop (cost-ratio cap bounded by
-    --adaptive-cap, alpha 0.5, delta 0.1) on the same resident workload."""
-    total = 5 + args.adaptive_steps
+    --adaptive-cap, alpha 0.5, delta 0.1) on the same resident workload; the
+    caps from the flop ratio, or from the cost ratios `rho` = (rho_H, rho_W)
+    when given; `steps` timed iterations after 5 untimed ones."""
+    steps = args.adaptive_steps if steps is None else steps
+    total = 5 + steps
+    extra = {} if rho is None else dict(inner_rho_h=rho[0], inner_rho_w=rho[1])
     solver = P.Solver(p.X, args.r, hp=3, beta0=0.5, gamma=1.01, gamma_bar=1.005, eta=1.5,
-                      inner_rule=P.Inner.ADAPTIVE, inner_k=args.adaptive_cap, max_iter=total)
+                      inner_rule=P.Inner.ADAPTIVE, inner_k=args.adaptive_cap, max_iter=total,
+                      **extra)
     solver.start(p.W0, p.H0, stream=stream)
     solver.iterate(5, stream=stream)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
-    solver.iterate(args.adaptive_steps, stream=stream)
+    solver.iterate(steps, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.adaptive_steps
+    ms = ev0.elapsed_time(ev1) / steps
     sw = solver.read_sweeps()
     res = solver.read(stream=stream)
     solver.close()
     timed = sw[5:]
+    caps = "flop ratio" if rho is None else f"device cost ratios rho_H {rho[0]:.1f}, rho_W {rho[1]:.1f}"
     return {"workload": f"planted dense {args.m}x{args.n} r={args.r}, E-A-HALS hp=3 with the adaptive "
-                        f"inner loop (alpha 0.5, delta 0.1, at most {args.adaptive_cap} sweeps)",
-            "value": 1e3 / ms, "unit": "iters/s", "ms_per_step": ms, "steps": args.adaptive_steps,
+                        f"inner loop (alpha 0.5, delta 0.1, caps from the {caps}, at most "
+                        f"{args.adaptive_cap} sweeps)",
+            "value": 1e3 / ms, "unit": "iters/s", "ms_per_step": ms, "steps": steps,
             "mean_sweeps_h": float(timed[:, 0].mean()), "mean_sweeps_w": float(timed[:, 1].mean()),
-            "rho_final": float(res.trace[-1])}
+            "iterations": int(res.n_iter), "rho_final": float(res.trace[-1]),
+            "trace_timed": [float(x) for x in res.trace[5:]]}
 
 
 def variant(args, P, S, p, stream, torch, x_dtype, prod, K, steps, label):
@@ -580,12 +599,25 @@ def main():
         _, v = variant(args, P, S, p, stream, torch, args.x_dtype, args.prod, 1, args.k1_steps,
                        f"planted dense {m}x{n} r={r}, one inner sweep per block (K=1)")
         out["inner_k1"] = v
+    # The adaptive loop again with its caps from the cost ratios of this
+    # device, measured in the fixed-K run above.
+    ad_dev = None
+    if ad is not None:
+        ad_dev = adaptive(args, P, p, stream, torch, device_cost_ratios(phases, K),
+                          steps=2 * args.adaptive_steps)
+        # Its error after the time the flop-ratio caps took for their timed
+        # iterations (iteration times are uniform within a run).
+        j = min(int(args.adaptive_steps * ad["ms_per_step"] / ad_dev["ms_per_step"]),
+                len(ad_dev["trace_timed"]) - 1)
+        ad_dev["rho_at_equal_time"] = ad_dev.pop("trace_timed")[j]
+        ad["rho_at_equal_time"] = ad.pop("trace_timed")[-1]
     cpu = cpu_baseline(args, p) if args.cpu_sample > 0 else None
     del p
     if ea is not None:
         out["eanls"] = ea
     if ad is not None:
         out["adaptive_inner"] = ad
+        out["adaptive_inner_device_cost"] = ad_dev
     if args.workload_steps > 0:
         out["workloads"] = workloads(args, P, S, stream, torch)
     if args.serve_requests > 0:

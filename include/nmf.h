@@ -66,9 +66,12 @@ typedef enum { NMF_X_F32 = 0, NMF_X_BF16 = 1, NMF_X_F16 = 2 } nmf_xdtype;
  * paper only says the rows are updated several times; this rule is recalled
  * from that work): on the W side at most floor(1 + inner_alpha rho_W) sweeps,
  * rho_W = 1 + (mn + nr) / (m (r + 1)) the cost of forming X H^T and H H^T
- * over that of one sweep (nnz for mn with sparse X), also capped at inner_k;
+ * over that of one sweep counted in flops (nnz for mn with sparse X), or
+ * inner_rho_w when it is positive (a cost ratio measured on the device, say:
+ * 1 + the side's X-pass time over one sweep's), also capped at inner_k;
  * after each sweep l >= 2 the loop stops once ||W^(l) - W^(l-1)||_F <=
- * inner_delta ||W^(1) - W^(0)||_F. The H side swaps m and n. Between sweeps
+ * inner_delta ||W^(1) - W^(0)||_F. The H side swaps m and n (and takes
+ * inner_rho_h). Between sweeps
  * the factor is kept in FP64. The sweeps run per iteration can be read with
  * nmf_read_sweeps. ADAPTIVE is not available to batched solves. */
 typedef enum { NMF_INNER_FIXED = 0, NMF_INNER_EXACT = 1, NMF_INNER_ADAPTIVE = 2 } nmf_inner;
@@ -140,6 +143,9 @@ typedef struct {
     int32_t flags;              /* NMF_FLAG_*                                   */
     double inner_alpha;         /* ADAPTIVE: cost-ratio weight, >= 0 (0.5)      */
     double inner_delta;         /* ADAPTIVE: stopping ratio, >= 0 (0.1)         */
+    double inner_rho_h;         /* ADAPTIVE: cost ratio of the H side, finite,
+                                   >= 0; 0 = the flop ratio (0)                 */
+    double inner_rho_w;         /* ADAPTIVE: the same for the W side (0)        */
 } nmf_params;
 
 void nmf_params_default(nmf_params *p);

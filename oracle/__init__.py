@@ -50,7 +50,8 @@ class _Params(C.Structure):
                 ("replay", C.c_void_p), ("inner_alpha", C.c_double),
                 ("inner_delta", C.c_double), ("sweeps_replay", C.c_void_p),
                 ("e2_scale", C.c_void_p), ("e2_scale_n", C.c_int),
-                ("resume", C.c_void_p), ("save", C.c_void_p)]
+                ("resume", C.c_void_p), ("save", C.c_void_p),
+                ("inner_rho_h", C.c_double), ("inner_rho_w", C.c_double)]
 
 
 def lib():
@@ -101,12 +102,14 @@ class _Held:
 def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
           eta=1.5, inner_k=10, max_iter=100, tol=0.0, flags=0, replay=None,
           inner_alpha=0.5, inner_delta=0.1, sweeps_replay=None, e2_scale=None,
-          resume=None, save=False):
+          resume=None, save=False, inner_rho_h=0.0, inner_rho_w=0.0):
     """Run Alg. 2 with Alg. 3 and return a dict with W, H (last accepted),
     trace (rho(0..n_iter)), accepted, beta, margin, beta_star (section 4,
     per iteration), sweeps (HALS sweeps on H and on W per iteration),
     sweep_margin (closest call of each adaptive stop decision) and n_iter.
     sweeps_replay forces the adaptive sweep counts ((max_iter, 2) array).
+    inner_rho_h, inner_rho_w > 0 replace the flop ratios of the adaptive
+    sweep caps (R18) by the caller's cost ratios of the two sides.
     e2_scale (test hook): factors applied to e(k)^2 for k = 0, 1, ... before
     the test of Algorithm 2 (NaN or inf drive its non-finite branch).
     save=True adds out["state"], the state after the last iteration (a dict:
@@ -153,7 +156,8 @@ def solve(X, r, W0, H0, *, hp=3, beta0=0.5, gamma=1.05, gamma_bar=1.01,
                   flags, None if rp is None else _ptr(rp).value, inner_alpha, inner_delta,
                   None if sr is None else _ptr(sr).value,
                   None if es is None else _ptr(es).value, 0 if es is None else es.size,
-                  None if rs is None else C.addressof(rs), None if sv is None else C.addressof(sv))
+                  None if rs is None else C.addressof(rs), None if sv is None else C.addressof(sv),
+                  inner_rho_h, inner_rho_w)
     nit = C.c_int(0)
     st = lib().oracle_eahals(C.byref(h.s), r, _ptr(W0), _ptr(H0), C.byref(prm),
                              _ptr(W), _ptr(H), _ptr(trace), _ptr(acc),

@@ -449,13 +449,16 @@ static void extrapolate(int64_t len, double beta, const double *N,
 /* --------------------------------------------- adaptive inner loop (R18) */
 
 /* Sweep cap of one side: floor(1 + alpha rho), rho = 1 + (mn + K r) / (R (r + 1)),
- * R the rows of the factor being updated and K the rows of the fixed one,
- * capped at inner_k and at least 1. */
+ * R the rows of the factor being updated and K the rows of the fixed one, or
+ * the caller's cost ratio of that side when it is positive; capped at inner_k
+ * and at least 1. */
 static int inner_cap(const oracle_matrix *X, int r, int w_side, const oracle_params *p)
 {
     const double m = (double)X->m, n = (double)X->n;
     const double mn = X->dense ? m * n : (double)X->row_ptr[X->m];
-    const double rho = w_side ? 1.0 + (mn + n * r) / (m * (r + 1.0))
+    const double given = w_side ? p->inner_rho_w : p->inner_rho_h;
+    const double rho = given > 0.0 ? given
+                     : w_side ? 1.0 + (mn + n * r) / (m * (r + 1.0))
                               : 1.0 + (mn + m * r) / (n * (r + 1.0));
     double cap = floor(1.0 + p->inner_alpha * rho);
     if (cap > p->inner_k) cap = p->inner_k;
@@ -508,7 +511,9 @@ int oracle_eahals(const oracle_matrix *X, int r, const double *W0,
         p->max_iter < 0 || p->inner_k < 1)
         return ORACLE_EINVAL;
     const int adaptive = (p->flags & ORACLE_ADAPTIVE_INNER) != 0;
-    if (adaptive && !(p->inner_alpha >= 0.0 && p->inner_delta >= 0.0)) return ORACLE_EINVAL;
+    if (adaptive && !(p->inner_alpha >= 0.0 && p->inner_delta >= 0.0 && p->inner_rho_h >= 0.0 &&
+                      p->inner_rho_w >= 0.0 && isfinite(p->inner_rho_h) && isfinite(p->inner_rho_w)))
+        return ORACLE_EINVAL;
     if (p->resume && (p->resume->k < 0 || p->resume->k > p->max_iter || !p->resume->W ||
                       !p->resume->H || !p->resume->Wy || !p->resume->Hy))
         return ORACLE_EINVAL;

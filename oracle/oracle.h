@@ -50,7 +50,8 @@
  *       times", not stated in the paper itself; parity unpinned against
  *       the paper): on the W side at most floor(1 + alpha rho_W) sweeps,
  *       rho_W = 1 + (mn + nr) / (m (r + 1)) (the cost of forming X H^T and
- *       H H^T over that of one sweep), capped at inner_k; stop after sweep
+ *       H H^T over that of one sweep, counted in flops), or the caller's
+ *       cost ratio of the side when given, capped at inner_k; stop after sweep
  *       l >= 2 once ||W^(l) - W^(l-1)||_F <= delta ||W^(1) - W^(0)||_F. The H
  *       side swaps m and n. Sparse X uses nnz for mn.
  *   R16 The diagnostic beta* of section 4 (the beta minimizing
@@ -128,6 +129,10 @@ typedef struct {
                                  solve continues with iteration resume->k + 1
                                  (trace[0..k] are left as they are)       */
     oracle_state *save;       /* NULL, or receives the state at the end     */
+    double inner_rho_h;       /* R18: the cost ratios rho_H, rho_W of the  */
+    double inner_rho_w;       /*   sweep caps when > 0 (a measured cost of  */
+                              /*   the side's X pass over one sweep, say);  */
+                              /*   0 takes the flop ratio                   */
 } oracle_params;
 
 /* Full solve (Alg. 2 with Alg. 3). Outputs, all caller-allocated:

@@ -89,7 +89,8 @@ class Params(C.Structure):
                 ("inner_k", C.c_int32), ("max_iter", C.c_int32),
                 ("tol", C.c_double), ("x_dtype", C.c_int32),
                 ("prod", C.c_int32), ("flags", C.c_int32),
-                ("inner_alpha", C.c_double), ("inner_delta", C.c_double)]
+                ("inner_alpha", C.c_double), ("inner_delta", C.c_double),
+                ("inner_rho_h", C.c_double), ("inner_rho_w", C.c_double)]
 
 
 _lib = None
@@ -223,7 +224,8 @@ class Solver:
     ``X`` is a float32 (m, n) numpy array, or an object with ``m, n,
     row_ptr, col_idx, val`` (CSR). Keyword arguments set nmf_params fields
     (hp, beta0, gamma, gamma_bar, eta, inner_rule, inner_k, inner_alpha,
-    inner_delta, max_iter, tol, x_dtype, prod, flags)."""
+    inner_delta, inner_rho_h, inner_rho_w, max_iter, tol, x_dtype, prod,
+    flags)."""
 
     def __init__(self, X, r, **params):
         self._ctx = C.c_void_p()

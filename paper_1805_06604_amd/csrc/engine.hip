@@ -139,6 +139,11 @@ nmf_status check_params(const nmf_params *p)
           std::isfinite(p->inner_delta)))
         return fail(nullptr, NMF_E_INVAL, "inner_alpha = %g and inner_delta = %g must be finite and >= 0",
                     p->inner_alpha, p->inner_delta);
+    if (p->inner_rule == NMF_INNER_ADAPTIVE &&
+        !(p->inner_rho_h >= 0.0 && std::isfinite(p->inner_rho_h) && p->inner_rho_w >= 0.0 &&
+          std::isfinite(p->inner_rho_w)))
+        return fail(nullptr, NMF_E_INVAL, "inner_rho_h = %g and inner_rho_w = %g must be finite and >= 0",
+                    p->inner_rho_h, p->inner_rho_w);
     if (p->inner_k < 1 || p->inner_k > 1000)
         return fail(nullptr, NMF_E_INVAL, "inner_k = %d must lie in 1..1000", p->inner_k);
     if (p->max_iter < 0 || p->max_iter > (1 << 28))
@@ -621,6 +626,8 @@ void nmf_params_default(nmf_params *p)
     p->flags = 0;
     p->inner_alpha = 0.5;
     p->inner_delta = 0.1;
+    p->inner_rho_h = 0.0;
+    p->inner_rho_w = 0.0;
 }
 
 nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
@@ -661,15 +668,16 @@ nmf_status nmf_create(const nmf_matrix *X, const nmf_params *p, nmf_ctx **out)
     c->b.beta_star_on = (c->p.flags & NMF_FLAG_BETA_STAR) != 0;
     if (p->inner_rule == NMF_INNER_ADAPTIVE) {
         // Sweep caps floor(1 + alpha rho), rho = 1 + (mn + K r) / (R (r + 1)) for
-        // R rows updated against K fixed ones (nnz for mn when X is sparse).
+        // R rows updated against K fixed ones (nnz for mn when X is sparse), or
+        // the caller's cost ratio of the side when it is positive.
         const double mn = X->fmt == NMF_CSR ? (double)X->nnz : (double)c->m * (double)c->n;
-        auto cap = [&](double rows, double fixed) {
-            const double rho = 1.0 + (mn + fixed * c->r) / (rows * (c->r + 1.0));
+        auto cap = [&](double rows, double fixed, double given) {
+            const double rho = given > 0.0 ? given : 1.0 + (mn + fixed * c->r) / (rows * (c->r + 1.0));
             const double k = std::floor(1.0 + p->inner_alpha * rho);
             return (int)std::max(1.0, std::min(k, (double)p->inner_k));
         };
-        c->cap_h = cap((double)c->n, (double)c->m);
-        c->cap_w = cap((double)c->m, (double)c->n);
+        c->cap_h = cap((double)c->n, (double)c->m, p->inner_rho_h);
+        c->cap_w = cap((double)c->m, (double)c->n, p->inner_rho_w);
     }
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking);
@@ -867,11 +875,11 @@ struct StateHeader {
     char magic[8];
     int32_t version, r, hp, inner_rule, inner_k, x_dtype, prod, flags, max_iter, stopped;
     int64_t m, n;
-    double beta0, gamma, gamma_bar, eta, tol, inner_alpha, inner_delta, nx2;
+    double beta0, gamma, gamma_bar, eta, tol, inner_alpha, inner_delta, inner_rho_h, inner_rho_w, nx2;
     uint64_t bytes;
 };
 constexpr char kStateMagic[8] = {'N', 'M', 'F', 'S', 'T', 'A', 'T', 'E'};
-constexpr int32_t kStateVersion = 1;
+constexpr int32_t kStateVersion = 2;
 
 // The device buffers that carry a solve from one iteration to the next: the
 // factor slots, the Gram buffers of the slots (with their inverse diagonals
@@ -951,6 +959,8 @@ nmf_status nmf_save_state(nmf_ctx *c, void *buf, size_t cap, void *stream)
     hd.tol = c->p.tol;
     hd.inner_alpha = c->p.inner_alpha;
     hd.inner_delta = c->p.inner_delta;
+    hd.inner_rho_h = c->p.inner_rho_h;
+    hd.inner_rho_w = c->p.inner_rho_w;
     hd.nx2 = c->nx2;
     hd.bytes = need;
     std::memcpy(out, &hd, sizeof(hd));
@@ -981,7 +991,8 @@ nmf_status nmf_load_state(nmf_ctx *c, const void *buf, size_t len, void *stream)
         hd.x_dtype != p.x_dtype || hd.prod != p.prod || hd.flags != p.flags ||
         hd.beta0 != p.beta0 || hd.gamma != p.gamma || hd.gamma_bar != p.gamma_bar ||
         hd.eta != p.eta || hd.tol != p.tol || hd.inner_alpha != p.inner_alpha ||
-        hd.inner_delta != p.inner_delta)
+        hd.inner_delta != p.inner_delta || hd.inner_rho_h != p.inner_rho_h ||
+        hd.inner_rho_w != p.inner_rho_w)
         return fail(c, NMF_E_INVAL, "the state was saved with other parameters");
     DevState h;
     std::memcpy(&h, in + sizeof(hd), sizeof(h));

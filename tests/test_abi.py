@@ -41,6 +41,7 @@ def test_defaults_are_the_papers_final_parameters():
     prm = P.make_params(20)
     assert (prm.hp, prm.beta0, prm.eta, prm.gamma, prm.gamma_bar) == (3, 0.5, 1.5, 1.01, 1.005)
     assert (prm.inner_rule, prm.inner_k, prm.inner_alpha, prm.inner_delta) == (P.Inner.FIXED, 10, 0.5, 0.1)
+    assert (prm.inner_rho_h, prm.inner_rho_w) == (0.0, 0.0)
 
 
 @pytest.mark.parametrize("kw,status", [
@@ -61,6 +62,8 @@ def test_defaults_are_the_papers_final_parameters():
     (dict(inner_rule=P.Inner.EXACT, inner_k=0), P.Status.E_INVAL),
     (dict(inner_rule=P.Inner.ADAPTIVE, inner_alpha=-0.5), P.Status.E_INVAL),
     (dict(inner_rule=P.Inner.ADAPTIVE, inner_delta=float("nan")), P.Status.E_INVAL),
+    (dict(inner_rule=P.Inner.ADAPTIVE, inner_rho_h=-1.0), P.Status.E_INVAL),
+    (dict(inner_rule=P.Inner.ADAPTIVE, inner_rho_w=float("inf")), P.Status.E_INVAL),
 ])
 def test_parameter_validation(kw, status):
     with pytest.raises(P.NMFError) as e:

@@ -115,3 +115,21 @@ def test_beta_star_with_the_adaptive_loop():
     tol = np.maximum(1e-6 * (1 + np.abs(bo)), 3 * np.abs(bf - bo))
     print("beta* (adaptive)", np.round(bo[:8], 4), "max dev", np.max(np.abs(bs - bo)), flush=True)
     assert np.all(np.abs(bs - bo) <= tol), np.max(np.abs(bs - bo) / tol)
+
+
+def test_given_cost_ratios_set_the_caps():
+    """Cost ratios given per side (as measured on the device, instead of the
+    flop ratio): rho_H = 7 and rho_W = 3 cap the loops at 4 and 2 sweeps, and
+    with delta = 0 every iteration runs exactly those counts, against the
+    oracle with the same ratios."""
+    sw = _check(S.lowrank(3, m=260, n=300, r=12), 30, hp=3, inner_delta=0.0,
+                inner_rho_h=7.0, inner_rho_w=3.0, **ALG)
+    assert np.all(sw[:, 0] == 4) and np.all(sw[:, 1] == 2)
+
+
+def test_given_cost_ratios_with_the_early_stop():
+    """The same ratios at delta = 0.1: the caps bound the counts and the
+    early stop decides below them, as the oracle's."""
+    sw = _check(S.lowrank(4, m=260, n=300, r=12), 30, hp=3, inner_rho_h=7.0,
+                inner_rho_w=3.0, **ALG)
+    assert sw[:, 0].max() <= 4 and sw[:, 1].max() <= 2

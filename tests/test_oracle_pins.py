@@ -668,6 +668,30 @@ def test_adaptive_sweep_cap(r, inner_k, alpha, cap):
     assert np.all(a["sweeps"] == cap)
 
 
+def test_adaptive_caps_from_given_cost_ratios():
+    """Cost ratios given per side replace the flop ratio: rho_H = 7 and
+    rho_W = 3 at alpha 0.5 cap the H loop at floor(4.5) = 4 and the W loop at
+    floor(2.5) = 2 sweeps; equal ratios of 7 on both sides, with delta = 0,
+    give the fixed loop of 4 sweeps bit for bit."""
+    p = S.lowrank(3)
+    a = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=8, inner_k=50, inner_delta=0.0,
+                     inner_rho_h=7.0, inner_rho_w=3.0, flags=oracle.ADAPTIVE_INNER)
+    assert np.all(a["sweeps"][:, 0] == 4) and np.all(a["sweeps"][:, 1] == 2)
+    b = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=8, inner_k=50, inner_delta=0.0,
+                     inner_rho_h=7.0, inner_rho_w=7.0, flags=oracle.ADAPTIVE_INNER)
+    c = oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=8, inner_k=4)
+    assert np.all(b["sweeps"] == 4)
+    np.testing.assert_array_equal(b["trace"], c["trace"])
+    np.testing.assert_array_equal(b["W"], c["W"])
+
+
+def test_adaptive_refuses_a_negative_cost_ratio():
+    p = S.lowrank(3)
+    with pytest.raises(RuntimeError):
+        oracle.solve(p.X, p.r, p.W0, p.H0, max_iter=2, inner_rho_w=-1.0,
+                     flags=oracle.ADAPTIVE_INNER)
+
+
 def test_adaptive_with_huge_delta_stops_after_the_second_sweep():
     """The stopping test applies from the second sweep on: with a delta no
     change can exceed, every loop runs exactly two sweeps."""
